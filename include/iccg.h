@@ -1,0 +1,221 @@
+/*
+ * iccg.h -- C ABI of the MI355X block-multicolored ICCG library (libiccg.so).
+ *
+ * The library solves A x = b for a symmetric positive definite sparse A with
+ * the conjugate gradient method preconditioned by IC(0), applied by forward
+ * and backward substitution over a block-multicolored ordering, as studied in
+ * "Comparison of Algebraic Block Multi-Coloring and Leiden Methods for
+ * Parallel Preconditioning in the ICCG Method":
+ *   - Section 3: ABMC blocking, block coloring, Algorithm 1 (forward
+ *     substitution: colors in sequence, the blocks of one color in parallel,
+ *     the rows of a block in ascending order), backward substitution in
+ *     reverse order;
+ *   - Section 4: Leiden blocking with modularity (Eq. 1) or CPM (Eq. 2);
+ *   - Section 5: stopping rule ||r||_2 / ||b||_2 <= tol;
+ *   - Section 6.1 / 7.1: greedy block coloring; Leiden blocks numbered by
+ *     descending size.
+ *
+ * Conventions for every function:
+ *   - int32 indices; CSR with ascending column indices inside each row and the
+ *     diagonal stored; nnz < 2^31.
+ *   - Host pointers are read during the call only and stay owned by the
+ *     caller.  "Device" pointers are HIP device memory owned by the caller
+ *     (for example torch tensors); the library never frees them.
+ *   - Every call returns an int status (ICCG_OK = 0 or a negative ICCG_E*);
+ *     no exception crosses the ABI.  iccg_last_error() gives a message for
+ *     the calling thread's last failure.
+ *   - A context is not thread safe; distinct contexts are independent.
+ *     Device work is enqueued on the context's stream (iccg_options.stream);
+ *     functions that return host-visible results synchronize that stream.
+ */
+#ifndef ICCG_H
+#define ICCG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ICCG_OK          0
+#define ICCG_EINVAL     -1  /* bad argument (null pointer, size, option)            */
+#define ICCG_EPATTERN   -2  /* pattern not symmetric, diagonal missing, unsorted    */
+#define ICCG_EBADORDER  -3  /* block_ptr/color_ptr malformed or same-color blocks adjacent */
+#define ICCG_EBREAKDOWN -4  /* non-positive or non-finite IC(0) pivot               */
+#define ICCG_ENOCONV    -5  /* maxit reached before the tolerance                    */
+#define ICCG_ENAN       -6  /* (p, Ap) <= 0 or a non-finite CG scalar                */
+#define ICCG_EHIP       -7  /* HIP runtime error                                     */
+#define ICCG_ENOMEM     -8  /* device or host allocation failed                      */
+#define ICCG_ESTATE     -9  /* call out of order (e.g. ic_apply before a factor)     */
+
+#define ICCG_FP64 0
+#define ICCG_FP32 1
+
+#define ICCG_QUALITY_MODULARITY 0
+#define ICCG_QUALITY_CPM        1
+
+typedef struct iccg_ctx iccg_ctx;
+
+typedef struct {
+    int   precision;    /* ICCG_FP64: factor and sweeps in FP64.  ICCG_FP32: factor
+                           stored and sweeps computed in FP32 (r is rounded to FP32
+                           on load, z widened to FP64 on store); CG vectors, dots and
+                           residuals stay FP64 either way.                        */
+    void *stream;       /* hipStream_t for all device work; NULL = null stream    */
+    int   check_every;  /* CG iterations enqueued between host reads of the
+                           device-side convergence flag (>= 1, default 32)        */
+    int   pack_rows;    /* max rows one wavefront task packs from consecutive small
+                           blocks of one color (1..64, default 64)                */
+    int   use_graph;    /* 1 = replay the iteration batch as a captured HIP graph  */
+} iccg_options;
+
+/* Fills *opt with the defaults above (FP64, null stream, 32, 64, 1). */
+void iccg_default_options(iccg_options *opt);
+
+/* ------------------------------------------------------------------------ */
+/* Host setup: ordering (deterministic for given inputs and seed)            */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * ABMC blocking with block size block_size (Section 3; s = ceil(n/n_b),
+ * Section 6.1), greedy block coloring (Section 6.1), color-major numbering.
+ * Inputs: pattern of A (rowptr[n+1], col[nnz]); values are not needed.
+ * Outputs (caller-allocated): perm[n] with perm[new] = old; *nblocks;
+ * block_ptr[nblocks+1] (capacity n+1): first new row of every block;
+ * *ncolors; color_ptr[ncolors+1] (capacity n+1): first block of every color.
+ * Blocks are numbered colors-first; within a color in blocking order; rows of
+ * a block keep ascending original index.
+ */
+int iccg_order_abmc(int n, const int *rowptr, const int *col, int block_size,
+                    int *perm, int *nblocks, int *block_ptr, int *ncolors, int *color_ptr);
+
+/*
+ * Leiden blocking (Section 4; Section 7.1 settings: beta = 0.01, two
+ * iterations) of the unweighted pattern graph with quality
+ * ICCG_QUALITY_MODULARITY (Eq. 1, resolution gamma) or ICCG_QUALITY_CPM
+ * (Eq. 2, resolution gamma); blocks renumbered by descending size (ties: the
+ * block holding the smaller original index first), then greedy coloring and
+ * color-major numbering as for ABMC.  Randomness: one SplitMix64 stream seeded
+ * with seed.  Outputs as iccg_order_abmc.
+ */
+int iccg_order_leiden(int n, const int *rowptr, const int *col, int quality, double gamma,
+                      double beta, int n_iter, uint64_t seed,
+                      int *perm, int *nblocks, int *block_ptr, int *ncolors, int *color_ptr);
+
+/*
+ * A' = P A P^T (perm[new] = old) with sorted columns.  prow[n+1], pcol[nnz],
+ * pval[nnz] are caller-allocated.
+ */
+int iccg_permute(int n, const int *rowptr, const int *col, const double *val, const int *perm,
+                 int *prow, int *pcol, double *pval);
+
+/* ------------------------------------------------------------------------ */
+/* Device path                                                               */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * Create a context for the permuted SPD matrix A' (host CSR; deep-copied to
+ * the device) and its ordering block_ptr[nblocks+1], color_ptr[ncolors+1].
+ * Validates: symmetric pattern, sorted columns, diagonal present
+ * (ICCG_EPATTERN); block_ptr monotone from 0 to n, color_ptr monotone from 0
+ * to nblocks, and no stored a'_ij joining two different blocks of one color
+ * (ICCG_EBADORDER).  Builds the per-wavefront substitution schedules for both
+ * sweeps.  opt may be NULL (defaults).  *out is NULL on failure.
+ */
+int iccg_setup(iccg_ctx **out, int n, const int *rowptr, const int *col, const double *val,
+               int nblocks, const int *block_ptr, int ncolors, const int *color_ptr,
+               const iccg_options *opt);
+
+/*
+ * IC(0) factor of A' (Section 3): L with pattern(L) = lower(A') and
+ * (L L^T)_ij = a'_ij on that pattern, computed in FP64 on the host and
+ * uploaded (rounded to FP32 for ICCG_FP32).  On a pivot that is not > 0 or
+ * not finite returns ICCG_EBREAKDOWN with *breakdown_row set (else -1); the
+ * context then holds no factor.
+ */
+int ic0_factor(iccg_ctx *c, int *breakdown_row);
+
+/*
+ * Install factor values computed elsewhere (the learned form) on the same
+ * pattern: lvals_dev is a DEVICE array of nnz FP64 values at the positions of
+ * A''s CSR, lower triangle including the diagonal used, upper ignored.
+ * Checks every diagonal entry is finite and > 0 and every off-diagonal value
+ * finite; on failure returns ICCG_EBREAKDOWN with *bad_row set and keeps the
+ * previous factor.
+ */
+int iccg_set_factor(iccg_ctx *c, const double *lvals_dev, int *bad_row);
+
+/* Copy the current factor (A' CSR positions, upper part zero) to host lvals[nnz]. */
+int iccg_get_factor(iccg_ctx *c, double *lvals);
+
+/*
+ * Preconditioner application z = (L L^T)^{-1} r (Algorithm 1 and the
+ * backward sweep).  r, z: DEVICE FP64 arrays of n; r is not modified; r and
+ * z must not alias.
+ */
+int ic_apply(iccg_ctx *c, const double *r, double *z);
+
+/* Forward sweep only, y = L^{-1} r (Algorithm 1).  DEVICE FP64 r, y. */
+int ic_forward(iccg_ctx *c, const double *r, double *y);
+
+/* Backward sweep only, z = L^{-T} y.  DEVICE FP64 y, z. */
+int ic_backward(iccg_ctx *c, const double *y, double *z);
+
+/* q = A' p (the CG step's SpMV); *pq_host (may be NULL) receives (p, q). DEVICE p, q. */
+int iccg_spmv(iccg_ctx *c, const double *p, double *q, double *pq_host);
+
+/* *out_host = (a, b), deterministic two-pass FP64 reduction.  DEVICE a, b of n. */
+int iccg_dot(iccg_ctx *c, const double *a, const double *b, double *out_host);
+
+/*
+ * PCG on A' x = b (Section 5): x = x0 (DEVICE, in/out), r = b - A'x, z = M^{-1} r,
+ * p = z; per iteration q = A'p, alpha = (r,z)/(p,q), x += alpha p, r -= alpha q,
+ * stop when ||r||_2/||b||_2 <= tol, else z = M^{-1} r, beta = (r,z)_new/(r,z),
+ * p = z + beta p.  Outputs: *iters, *relres (recursive), *relres_true
+ * (||b - A'x||/||b|| recomputed at exit); any may be NULL.  Returns ICCG_OK,
+ * ICCG_ENOCONV (x = last iterate), ICCG_ENAN, or ICCG_ESTATE without a factor.
+ * b, x: DEVICE FP64 arrays of n.
+ */
+int iccg_solve(iccg_ctx *c, const double *b, double *x, double tol, int maxit,
+               int *iters, double *relres, double *relres_true);
+
+/*
+ * iccg_solve run eagerly with a HIP event pair around every SpMV and every
+ * per-color sweep launch (the phase split of the paper's Table 8: forward
+ * substitution, backward substitution, SpMV, other).  Same arguments and
+ * return as iccg_solve; out[10] (host) receives: [0] device time of the solve
+ * in ms, [1] SpMV ms, [2] forward-sweep ms, [3] backward-sweep ms (sums of
+ * per-launch durations), [4] the rest (reductions, vector updates, launch
+ * gaps), [5] forward launches, [6] backward launches, [7] SpMV launches,
+ * [8] iterations, [9] true relative residual.
+ */
+int iccg_profile_solve(iccg_ctx *c, const double *b, double *x, double tol, int maxit,
+                       double *out);
+
+/* Residual history of the last iccg_solve: hist[k] = ||r_k||/||b||, k = 0..iters
+ * (capacity cap); returns the number written or a negative status. */
+int iccg_residual_history(iccg_ctx *c, double *hist, int cap);
+
+typedef struct {
+    int    n, nnz, nnz_lower;      /* nnz_lower: strictly lower entries          */
+    int    nblocks, ncolors;
+    int    ntasks_fwd, nchunks_fwd; /* wavefront tasks / 64-row chunks, forward   */
+    int    max_block, max_depth;    /* largest block; deepest intra-chunk level   */
+    int    precision;
+    int    has_factor;
+    double sweep_bytes;             /* algorithmic bytes of one sweep (precision) */
+    double spmv_bytes;              /* algorithmic bytes of one SpMV              */
+    double last_solve_ms;           /* device time of the last iccg_solve         */
+    int    last_iters;
+} iccg_info;
+
+int iccg_get_info(iccg_ctx *c, iccg_info *info);
+
+const char *iccg_strerror(int status);
+const char *iccg_last_error(void);
+void iccg_destroy(iccg_ctx *c);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ICCG_H */

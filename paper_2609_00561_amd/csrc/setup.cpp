@@ -1,0 +1,153 @@
+// Host-side setup of the substitution schedules and the host IC(0) factor.
+//
+// Algorithm 1 (Section 3) runs the colors in sequence, the blocks of one color
+// in parallel and the rows of a block in ascending order; the backward sweep
+// runs the same scheme in reverse.  Here the blocks of one color are packed
+// into wavefront-sized chunks and, inside a chunk, every row gets the level of
+// its longest chain of in-chunk dependencies.  Rows of one level only read
+// values that are final (earlier colors, earlier chunks, lower levels), so
+// computing them together gives each row exactly the terms of the in-order
+// sweep.
+#include "iccg_internal.h"
+
+#include <algorithm>
+#include <cmath>
+
+namespace iccg {
+
+namespace {
+
+struct RowEntries {
+    std::vector<int> ext, inn;   // CSR positions: before-chunk / in-chunk dependencies
+};
+
+}  // namespace
+
+int build_sweep_plan(bool forward, int n, const int *rowptr, const int *col, const int *tpos,
+                     int nblocks, const int *block_ptr, int ncolors, const int *color_ptr,
+                     int pack_rows, SweepPlan &out) {
+    (void)nblocks;
+    out = SweepPlan();
+    out.forward = forward;
+    out.meta.assign(n, 0);
+    if (pack_rows < 1 || pack_rows > kChunkRows) pack_rows = kChunkRows;
+
+    // 1. chunk boundaries, grouped into tasks, color by color
+    std::vector<std::pair<int, int>> chunk_rows;   // [row0, row1)
+    out.color_task_ptr.push_back(0);
+    out.task_chunk_ptr.push_back(0);
+    auto close_task = [&]() { out.task_chunk_ptr.push_back(static_cast<int>(chunk_rows.size())); };
+    for (int c = 0; c < ncolors; ++c) {
+        int open0 = -1, open1 = -1;
+        auto flush = [&]() {
+            if (open0 >= 0) {
+                chunk_rows.emplace_back(open0, open1);
+                close_task();
+                open0 = open1 = -1;
+            }
+        };
+        for (int b = color_ptr[c]; b < color_ptr[c + 1]; ++b) {
+            const int r0 = block_ptr[b], r1 = block_ptr[b + 1], size = r1 - r0;
+            if (size > kChunkRows) {
+                flush();
+                for (int r = r0; r < r1; r += kChunkRows) chunk_rows.emplace_back(r, std::min(r + kChunkRows, r1));
+                close_task();
+            } else {
+                if (open0 >= 0 && (open1 - open0) + size > pack_rows) flush();
+                if (open0 < 0) open0 = open1 = r0;
+                open1 = r1;
+            }
+        }
+        flush();
+        out.color_task_ptr.push_back(static_cast<int>(out.task_chunk_ptr.size()) - 1);
+    }
+
+    // 2. per chunk: classify entries, levels, slot layout
+    long long nslots = 0;
+    RowEntries rows[kChunkRows];
+    int level[kChunkRows];
+    for (const auto &cr : chunk_rows) {
+        const int r0 = cr.first, r1 = cr.second, nr = r1 - r0;
+        int width = 0, depth = 0;
+        for (int step = 0; step < nr; ++step) {
+            const int t = forward ? step : nr - 1 - step;
+            const int i = r0 + t;
+            RowEntries &re = rows[t];
+            re.ext.clear();
+            re.inn.clear();
+            int lev = 0;
+            for (int k = rowptr[i]; k < rowptr[i + 1]; ++k) {
+                const int j = col[k];
+                if (forward ? (j >= i) : (j <= i)) continue;
+                const bool inside = (j >= r0 && j < r1);
+                if (inside) {
+                    re.inn.push_back(k);
+                    lev = std::max(lev, level[j - r0] + 1);
+                } else {
+                    re.ext.push_back(k);
+                }
+            }
+            level[t] = lev;
+            if (re.ext.size() > 0xffff) return set_error(ICCG_EINVAL, "a row has more than 65535 off-diagonal entries in one triangle");
+            width = std::max(width, static_cast<int>(re.ext.size() + re.inn.size()));
+            depth = std::max(depth, lev + 1);
+            out.meta[i] = pack_meta(static_cast<int>(re.ext.size()), static_cast<int>(re.inn.size()), lev);
+        }
+        if (nslots + static_cast<long long>(width) * nr >= (1LL << 31))
+            return set_error(ICCG_EINVAL, "substitution schedule exceeds 2^31 slots");
+        Chunk ch;
+        ch.row0 = r0;
+        ch.off = static_cast<int32_t>(nslots);
+        ch.nrows = static_cast<int16_t>(nr);
+        ch.width = static_cast<int16_t>(width);
+        ch.depth = static_cast<int16_t>(depth);
+        ch.pad = 0;
+        out.chunks.push_back(ch);
+        out.max_depth = std::max(out.max_depth, depth);
+        out.slot_col.resize(nslots + static_cast<long long>(width) * nr, -1);
+        out.slot_src.resize(nslots + static_cast<long long>(width) * nr, -1);
+        for (int t = 0; t < nr; ++t) {
+            int k = 0;
+            for (const auto *grp : {&rows[t].ext, &rows[t].inn})
+                for (int pos : *grp) {
+                    const long long slot = nslots + static_cast<long long>(k) * nr + t;
+                    out.slot_col[slot] = col[pos];
+                    out.slot_src[slot] = forward ? pos : tpos[pos];
+                    ++k;
+                }
+        }
+        nslots += static_cast<long long>(width) * nr;
+    }
+    return ICCG_OK;
+}
+
+// Row-by-row IC(0): for every k < i in the pattern of row i (ascending),
+//   L_ik = (a_ik - sum_j L_ij L_kj) / L_kk   over j < k in both patterns,
+// then L_ii = sqrt(a_ii - sum_k L_ik^2).  Row i's finished values are
+// scattered into a position map so the inner sum walks row k only.
+int ic0_host(int n, const int *rowptr, const int *col, const double *val, const int *dpos,
+             std::vector<double> &lval) {
+    lval.assign(static_cast<size_t>(rowptr[n]), 0.0);
+    std::vector<int> where(n, -1);
+    for (int i = 0; i < n; ++i) {
+        const int d = dpos[i];
+        for (int p = rowptr[i]; p < d; ++p) where[col[p]] = p;
+        double pivot = val[d];
+        for (int p = rowptr[i]; p < d; ++p) {
+            const int k = col[p];
+            double s = val[p];
+            for (int q = rowptr[k]; q < dpos[k]; ++q) {
+                const int w = where[col[q]];
+                if (w >= 0) s -= lval[w] * lval[q];
+            }
+            lval[p] = s / lval[dpos[k]];
+        }
+        for (int p = rowptr[i]; p < d; ++p) pivot -= lval[p] * lval[p];
+        for (int p = rowptr[i]; p < d; ++p) where[col[p]] = -1;
+        if (!(pivot > 0.0) || !std::isfinite(pivot)) return i;
+        lval[d] = std::sqrt(pivot);
+    }
+    return -1;
+}
+
+}  // namespace iccg
