@@ -31,6 +31,7 @@
 #include <memory>
 #include <new>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 namespace iccg {
@@ -90,7 +91,17 @@ enum ReduceOp : int {
 };
 
 constexpr int kVecThreads = 256;
-constexpr int kMaxVecBlocks = 2048;
+constexpr int kReduceThreads = 1024;
+constexpr int kMaxVecBlocks = 2048;   // multiple of 8
+
+// Workgroups are dealt to the 8 XCDs round robin; give each XCD one
+// contiguous range of logical blocks so neighbouring rows share an L2.
+// A bijection on [0, G).
+__device__ inline int xcd_remap(int b, int G) {
+    const int x = b & 7, i = b >> 3;
+    const int q = G >> 3, r = G & 7;
+    return x * q + min(x, r) + i;
+}
 
 // ---------------------------------------------------------------------------
 // reductions
@@ -101,28 +112,29 @@ __device__ inline double wave_sum(double v) {
     return v;
 }
 
-// Deterministic sum over a workgroup of kVecThreads threads; result valid in
-// thread 0.
+// Deterministic sum over a workgroup of NT threads; result valid in thread 0.
+template <int NT>
 __device__ inline double block_sum(double v) {
-    __shared__ double red[kVecThreads / 64];
+    __shared__ double red[NT / 64];
     v = wave_sum(v);
     const int w = threadIdx.x >> 6;
     if ((threadIdx.x & 63) == 0) red[w] = v;
     __syncthreads();
     double s = 0.0;
     if (threadIdx.x == 0)
-        for (int k = 0; k < kVecThreads / 64; ++k) s += red[k];
+        for (int k = 0; k < NT / 64; ++k) s += red[k];
     return s;
 }
 
-__global__ __launch_bounds__(kVecThreads) void k_reduce(const double *__restrict__ part, int np,
-                                                        DevScalars *sc, int op,
-                                                        double *__restrict__ out,
-                                                        double *__restrict__ hist) {
+__global__ __launch_bounds__(kReduceThreads) void k_reduce(const double *__restrict__ part,
+                                                           int np, DevScalars *sc, int op,
+                                                           double *__restrict__ out,
+                                                           double *__restrict__ hist) {
     if (op != OP_STORE && op != OP_TRUE && op != OP_BNORM && sc->done != DONE_RUNNING) return;
     double v = 0.0;
-    for (int k = threadIdx.x; k < np; k += kVecThreads) v += part[k];
-    v = block_sum(v);
+#pragma unroll 8
+    for (int k = threadIdx.x; k < np; k += kReduceThreads) v += part[k];
+    v = block_sum<kReduceThreads>(v);
     if (threadIdx.x != 0) return;
     switch (op) {
         case OP_STORE: out[0] = v; break;
@@ -178,93 +190,111 @@ __global__ void k_init_scalars(DevScalars *sc, double tol, int maxit, int hist_c
 }
 
 // ---------------------------------------------------------------------------
-// SpMV, CSR with G lanes per row (G = 4..64, chosen from the mean row length)
-// MODE 0: y = A x, partial (x, y).   MODE 1: y = b - A x, partial (y, y).
+// SpMV on the sliced ELL copy (one wavefront per 64-row slice, one lane per row)
+//   SP_PLAIN: y = A x, partial (x, y)
+//   SP_RESID: y = b - A x, partial (y, y)
+//   SP_CG:    p_new = z + beta p_old (formed on the fly for every gathered
+//             entry and stored for the own row), y = A p_new, partial (p_new, y);
+//             x is p_old here.
 // ---------------------------------------------------------------------------
-template <int G, int MODE>
-__global__ __launch_bounds__(kVecThreads) void k_spmv(int n, const int *__restrict__ rowptr,
-                                                      const int *__restrict__ col,
-                                                      const double *__restrict__ val,
-                                                      const double *__restrict__ x,
-                                                      double *__restrict__ y,
-                                                      const double *__restrict__ b,
-                                                      double *__restrict__ part,
-                                                      const DevScalars *sc) {
+enum SpmvMode : int { SP_PLAIN = 0, SP_RESID = 1, SP_CG = 2 };
+
+// One wavefront workgroup per slice (grid-stride over slices); WMAX slots of a
+// row are loaded into registers at once, then all gathers, then the row sum in
+// ascending column order.
+template <int MODE, int WMAX>
+__global__ __launch_bounds__(64) void k_spmv(int n, int nslices, const int *__restrict__ slice_off,
+                                             const int *__restrict__ slice_w,
+                                             const int *__restrict__ col,
+                                             const double *__restrict__ val,
+                                             const double *__restrict__ x,
+                                             double *__restrict__ y,
+                                             const double *__restrict__ b,
+                                             const double *__restrict__ z,
+                                             double *__restrict__ pnew,
+                                             double *__restrict__ part,
+                                             const DevScalars *sc) {
     if (sc && sc->done != DONE_RUNNING) return;
-    constexpr int RPW = kVecThreads / G;  // rows per workgroup pass
-    const int lane = threadIdx.x % G;
-    const int grp = threadIdx.x / G;
+    const int lane = threadIdx.x;
+    const int wg = xcd_remap(blockIdx.x, gridDim.x);
+    const double beta = (MODE == SP_CG) ? sc->beta : 0.0;
     double acc = 0.0;
-    for (int row0 = blockIdx.x * RPW; row0 < n; row0 += gridDim.x * RPW) {
-        const int row = row0 + grp;
-        double s = 0.0;
+    for (int sl = wg; sl < nslices; sl += gridDim.x) {
+        const int off = slice_off[sl] + lane, w = slice_w[sl];
+        const int row = sl * 64 + lane;
+        int cc[WMAX];
+        double vv[WMAX], xv[WMAX];
+#pragma unroll
+        for (int k = 0; k < WMAX; ++k)
+            if (k < w) {
+                cc[k] = col[off + k * 64];
+                vv[k] = val[off + k * 64];
+            }
+        double own_z = 0.0, own_x = 0.0, own_b = 0.0;
         if (row < n) {
-            const int a = rowptr[row], e = rowptr[row + 1];
-            for (int k = a + lane; k < e; k += G) s += val[k] * x[col[k]];
+            own_x = x[row];
+            if (MODE == SP_CG) own_z = z[row];
+            if (MODE == SP_RESID) own_b = b[row];
         }
-        for (int off = G / 2; off > 0; off >>= 1) s += __shfl_xor(s, off, G);
-        if (lane == 0 && row < n) {
-            if (MODE == 0) {
-                y[row] = s;
-                acc += x[row] * s;
-            } else {
-                const double rv = b[row] - s;
+        double zv[WMAX];
+#pragma unroll
+        for (int k = 0; k < WMAX; ++k)
+            if (k < w) {
+                const int c = cc[k] < 0 ? 0 : cc[k];
+                xv[k] = x[c];
+                if (MODE == SP_CG) zv[k] = z[c];
+            }
+        double sum = 0.0;
+#pragma unroll
+        for (int k = 0; k < WMAX; ++k)
+            if (k < w) {
+                const double v = (MODE == SP_CG) ? zv[k] + beta * xv[k] : xv[k];
+                sum = (cc[k] >= 0) ? sum + vv[k] * v : sum;
+            }
+        for (int k = WMAX; k < w; ++k) {
+            const int c = col[off + k * 64];
+            if (c >= 0) {
+                const double v = (MODE == SP_CG) ? z[c] + beta * x[c] : x[c];
+                sum += val[off + k * 64] * v;
+            }
+        }
+        if (row < n) {
+            if (MODE == SP_PLAIN) {
+                y[row] = sum;
+                acc += own_x * sum;
+            } else if (MODE == SP_RESID) {
+                const double rv = own_b - sum;
                 y[row] = rv;
                 acc += rv * rv;
+            } else {
+                const double pn = own_z + beta * own_x;
+                pnew[row] = pn;
+                y[row] = sum;
+                acc += pn * sum;
             }
         }
     }
-    const double t = block_sum(acc);
+    const double t = wave_sum(acc);
     if (threadIdx.x == 0) part[blockIdx.x] = t;
 }
 
 // ---------------------------------------------------------------------------
-// BLAS-1 pieces of the CG step
+// BLAS-1 helpers
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kVecThreads) void k_dot(int n, const double *__restrict__ a,
                                                      const double *__restrict__ b,
                                                      double *__restrict__ part) {
     double acc = 0.0;
-    for (int i = blockIdx.x * kVecThreads + threadIdx.x; i < n; i += gridDim.x * kVecThreads)
+    const int wg = xcd_remap(blockIdx.x, gridDim.x);
+    for (int i = wg * kVecThreads + threadIdx.x; i < n; i += gridDim.x * kVecThreads)
         acc += a[i] * b[i];
-    const double t = block_sum(acc);
+    const double t = block_sum<kVecThreads>(acc);
     if (threadIdx.x == 0) part[blockIdx.x] = t;
 }
 
-__global__ __launch_bounds__(kVecThreads) void k_update_xr(int n, double *__restrict__ x,
-                                                           double *__restrict__ r,
-                                                           const double *__restrict__ p,
-                                                           const double *__restrict__ q,
-                                                           const DevScalars *sc,
-                                                           double *__restrict__ part) {
-    if (sc->done != DONE_RUNNING) return;
-    const double alpha = sc->alpha;
-    double acc = 0.0;
-    for (int i = blockIdx.x * kVecThreads + threadIdx.x; i < n; i += gridDim.x * kVecThreads) {
-        x[i] += alpha * p[i];
-        const double ri = r[i] - alpha * q[i];
-        r[i] = ri;
-        acc += ri * ri;
-    }
-    const double t = block_sum(acc);
-    if (threadIdx.x == 0) part[blockIdx.x] = t;
-}
-
-__global__ __launch_bounds__(kVecThreads) void k_update_p(int n, double *__restrict__ p,
-                                                          const double *__restrict__ z,
-                                                          const DevScalars *sc) {
-    if (sc->done != DONE_RUNNING) return;
-    const double beta = sc->beta;
+__global__ __launch_bounds__(kVecThreads) void k_fill(int n, double *__restrict__ dst, double v) {
     for (int i = blockIdx.x * kVecThreads + threadIdx.x; i < n; i += gridDim.x * kVecThreads)
-        p[i] = z[i] + beta * p[i];
-}
-
-__global__ __launch_bounds__(kVecThreads) void k_copy(int n, double *__restrict__ dst,
-                                                      const double *__restrict__ src,
-                                                      const DevScalars *sc) {
-    if (sc && sc->done != DONE_RUNNING) return;
-    for (int i = blockIdx.x * kVecThreads + threadIdx.x; i < n; i += gridDim.x * kVecThreads)
-        dst[i] = src[i];
+        dst[i] = v;
 }
 
 template <typename A, typename B>
@@ -325,69 +355,142 @@ __global__ void k_check_factor(int n, const int *__restrict__ rowptr, const int 
 // ---------------------------------------------------------------------------
 // substitution sweep over the tasks of one color
 // ---------------------------------------------------------------------------
+template <typename F>
 struct SweepArgs {
-    const int *task_chunk_ptr;
+    const TaskRec *tasks;
     const Chunk *chunks;
     const uint32_t *meta;
     const int *scol;
-    const void *sval;   // F[nslots]
-    const void *inv;    // F[n], 1 / L_ii
+    const F *sval;
+    const F *inv;      // 1 / L_ii
 };
 
-// FWD: y_i = (r_i - sum_{j<i} L_ij y_j) / L_ii over the rows of the color.
-// !FWD: z_i = (y_i - sum_{j>i} L_ji z_j) / L_ii; with rdot != null each task
-// also writes sum over its rows of rdot_i * z_i to part[task].
-// TIn is the right-hand side type, TOut the solution type (read back for
-// dependencies); the arithmetic is in F.
-template <typename F, bool FWD, typename TIn, typename TOut>
-__global__ __launch_bounds__(64) void k_sweep(SweepArgs a, int task_base,
-                                              const TIn *__restrict__ in, TOut *__restrict__ out,
-                                              const double *__restrict__ rdot,
-                                              double *__restrict__ part, const DevScalars *sc) {
-    if (sc && sc->done != DONE_RUNNING) return;
-    __shared__ F ys[kChunkRows];
-    const F *__restrict__ sval = static_cast<const F *>(a.sval);
-    const F *__restrict__ inv = static_cast<const F *>(a.inv);
-    const int task = task_base + blockIdx.x;
-    const int c0 = a.task_chunk_ptr[task], c1 = a.task_chunk_ptr[task + 1];
+// SW_APPLY: plain sweep.  SW_CG_FWD: forward sweep that first applies the CG
+// update of its own rows (x += alpha p, r -= alpha q) and substitutes the new
+// r, with part[task] = sum of r_i^2.  SW_DOT_BWD: backward sweep with
+// part[task] = sum of rdot_i z_i.
+enum SweepMode : int { SW_APPLY = 0, SW_CG_FWD = 1, SW_DOT_BWD = 2 };
+
+struct CgArgs {
+    double *x;
+    double *r;
+    const double *p;
+    const double *q;
+    const double *rdot;
+    double *part;
+    const DevScalars *sc;
+};
+
+// One chunk of a task: see k_sweep.
+template <typename F, bool FWD, int KMAX, int MODE, typename TIn, typename TOut>
+__device__ __forceinline__ void sweep_chunk(const Chunk &ch, const uint32_t *__restrict__ meta,
+                                            const int *__restrict__ scol,
+                                            const F *__restrict__ sval,
+                                            const F *__restrict__ inv,
+                                            const TIn *__restrict__ in, TOut *__restrict__ out,
+                                            const CgArgs &cg, double alpha, F *ys, double &dacc) {
     const int t = threadIdx.x;
-    double dacc = 0.0;
-    for (int q = 0; q < c1 - c0; ++q) {
-        const Chunk ch = a.chunks[FWD ? c0 + q : c1 - 1 - q];
-        const int nr = ch.nrows;
-        const bool active = t < nr;
-        const int i = ch.row0 + t;
-        F s = F(0), dinv = F(0);
-        uint32_t m = 0;
-        if (active) {
-            s = static_cast<F>(in[i]);
-            m = a.meta[i];
-            dinv = inv[i];
-        }
-        const int ne = m & 0xffffu, ni = (m >> 16) & 0xffu, lev = m >> 24;
-        const F *v = sval + ch.off + t;
-        const int *cj = a.scol + ch.off + t;
-        // terms already final before this chunk: all lanes at once
-        for (int k = 0; k < ne; ++k) s -= v[k * nr] * static_cast<F>(out[cj[k * nr]]);
-        // in-chunk terms, level by level
-        for (int L = 0; L < ch.depth; ++L) {
-            if (active && lev == L) {
-                for (int k = ne; k < ne + ni; ++k) s -= v[k * nr] * ys[cj[k * nr] - ch.row0];
-                ys[t] = s * dinv;
+    const int nr = ch.shape & 0xffff, W = ch.shape >> 16;
+    const bool active = t < nr;
+    const int i = ch.row0 + t;
+    const int base = ch.off + t;
+    F vv[KMAX];
+    int cc[KMAX];
+    uint32_t m = 0;
+    F s = F(0), dinv = F(0);
+    double rd = 0.0;
+    if (active) {
+        // every independent load of the chunk first, so they overlap
+#pragma unroll
+        for (int k = 0; k < KMAX; ++k)
+            if (k < W) {
+                vv[k] = sval[base + k * nr];
+                cc[k] = scol[base + k * nr];
             }
-            __syncthreads();
+        m = meta[i];
+        dinv = inv[i];
+        if (MODE == SW_CG_FWD) {
+            const double pi = cg.p[i], qi = cg.q[i], xi = cg.x[i], r0 = cg.r[i];
+            const double ri = r0 - alpha * qi;
+            cg.x[i] = xi + alpha * pi;
+            cg.r[i] = ri;
+            dacc += ri * ri;
+            s = static_cast<F>(ri);
+        } else {
+            s = static_cast<F>(in[i]);
         }
-        if (active) {
-            const F yv = ys[t];
-            out[i] = static_cast<TOut>(yv);
-            if (rdot) dacc += rdot[i] * static_cast<double>(yv);
-        }
-        // later chunks of this task read this chunk's results from memory
-        if (q + 1 < c1 - c0) __syncthreads();
+        if (MODE == SW_DOT_BWD) rd = cg.rdot[i];
     }
-    if (part) {
+    const int ne = m & 0xffffu, ni = (m >> 16) & 0xffu, lev = m >> 24;
+    if (active) {
+        // all gathers at once (the chunk width is uniform); slots that are not
+        // before-chunk terms read a harmless valid address and are discarded
+        F g[KMAX];
+#pragma unroll
+        for (int k = 0; k < KMAX; ++k)
+            if (k < W) g[k] = static_cast<F>(out[cc[k] < 0 ? 0 : cc[k]]);
+#pragma unroll
+        for (int k = 0; k < KMAX; ++k)
+            if (k < W) s = (k < ne) ? s - vv[k] * g[k] : s;
+        for (int k = KMAX; k < ne; ++k) {
+            const int sl = base + k * nr;
+            s -= sval[sl] * static_cast<F>(out[scol[sl]]);
+        }
+    }
+    for (int L = 0; L < ch.depth; ++L) {
+        if (active && lev == L) {
+#pragma unroll
+            for (int k = 0; k < KMAX; ++k)
+                if (k >= ne && k < ne + ni) s -= vv[k] * ys[cc[k] - ch.row0];
+            for (int k = max(KMAX, ne); k < ne + ni; ++k) {
+                const int sl = base + k * nr;
+                s -= sval[sl] * ys[scol[sl] - ch.row0];
+            }
+            ys[t] = s * dinv;
+        }
+        __syncthreads();
+    }
+    if (active) {
+        const F yv = ys[t];
+        out[i] = static_cast<TOut>(yv);
+        if (MODE == SW_DOT_BWD) dacc += rd * static_cast<double>(yv);
+    }
+}
+
+// FWD: y_i = (r_i - sum_{j<i} L_ij y_j) / L_ii over the rows of one color.
+// !FWD: z_i = (y_i - sum_{j>i} L_ji z_j) / L_ii.
+// One wavefront per task, one lane per row of the current chunk.  All of the
+// chunk's slots (up to KMAX per row in registers) are loaded at once, then all
+// gathers of values final before the chunk, then the in-chunk terms level by
+// level through LDS.  The per-row subtraction order is: before-chunk terms in
+// ascending column order, then in-chunk terms in ascending column order.
+template <typename F, bool FWD, int KMAX, int MODE, typename TIn, typename TOut>
+__global__ __launch_bounds__(64) void k_sweep(const TaskRec *__restrict__ tasks,
+                                              const Chunk *__restrict__ chunks,
+                                              const uint32_t *__restrict__ meta,
+                                              const int *__restrict__ scol,
+                                              const F *__restrict__ sval,
+                                              const F *__restrict__ inv, int task_base,
+                                              int ntasks_color, const TIn *__restrict__ in,
+                                              TOut *__restrict__ out, CgArgs cg) {
+    if (cg.sc && cg.sc->done != DONE_RUNNING) return;
+    __shared__ F ys[kChunkRows];
+    const int task = task_base + xcd_remap(blockIdx.x, ntasks_color);
+    const TaskRec tr = tasks[task];
+    const double alpha = (MODE == SW_CG_FWD) ? cg.sc->alpha : 0.0;
+    double dacc = 0.0;
+    sweep_chunk<F, FWD, KMAX, MODE, TIn, TOut>(tr.first, meta, scol, sval, inv, in, out, cg, alpha,
+                                               ys, dacc);
+    for (int q = 1; q < tr.nchunks; ++q) {
+        // later chunks of this task read earlier chunks' results from memory
+        __syncthreads();
+        const Chunk ch = chunks[FWD ? tr.c0 + q : tr.c1 - 1 - q];
+        sweep_chunk<F, FWD, KMAX, MODE, TIn, TOut>(ch, meta, scol, sval, inv, in, out, cg, alpha,
+                                                   ys, dacc);
+    }
+    if (MODE != SW_APPLY) {
         const double tsum = wave_sum(dacc);
-        if (t == 0) part[task] = tsum;
+        if (threadIdx.x == 0) cg.part[task] = tsum;
     }
 }
 
@@ -429,8 +532,10 @@ struct DevSweep {
     int ntasks = 0;
     long long nslots = 0;
     int max_depth = 0;
+    int max_width = 0;
+    int kmax = 4;                      // register slots per row in k_sweep
     std::vector<int> color_task_ptr;
-    DevArray<int> task_chunk_ptr;
+    DevArray<TaskRec> tasks;
     DevArray<Chunk> chunks;
     DevArray<uint32_t> meta;
     DevArray<int> scol, ssrc;
@@ -496,13 +601,17 @@ struct iccg_ctx {
     DevArray<double> inv64;
     DevArray<float> inv32;
     bool has_factor = false;
-    DevArray<double> x, r, z, p, q, b, y64;
+    DevArray<double> x, r, z, q, b, y64;
+    DevArray<double> pbuf[2];       // search direction, double buffered across iterations
     DevArray<float> y32;
     DevArray<double> part, hist;
     DevArray<DevScalars> scal;
     DevArray<int> dint;
     DevScalars *h_scal = nullptr;   // pinned
-    int spmv_lanes = 8;
+    int nslices = 0;                // sliced ELL copy of A' for the SpMV
+    int sell_wmax = 8;              // register slots per row in k_spmv
+    DevArray<int> sell_off, sell_w, sell_col;
+    DevArray<double> sell_val;
     int spmv_blocks = 1, vec_blocks = 1;
     hipGraphExec_t graph = nullptr;
     int graph_iters = 0;
@@ -546,40 +655,36 @@ int grid_for(long long items, int threads, int cap) {
 }
 
 int launch_spmv(iccg_ctx *c, int mode, const double *x, double *y, const double *b,
-                const DevScalars *sc) {
-    const int G = c->spmv_lanes;
-    dim3 grid(c->spmv_blocks), block(kVecThreads);
+                const double *z, double *pnew, const DevScalars *sc) {
+    dim3 grid(c->spmv_blocks), block(64);
     if (c->prof) c->prof->begin(c->work);
-#define SPMV_CASE(GG)                                                                          \
-    case GG:                                                                                   \
-        if (mode == 0)                                                                         \
-            hipLaunchKernelGGL((k_spmv<GG, 0>), grid, block, 0, c->work, c->n, c->rowptr.p,    \
-                               c->col.p, c->val.p, x, y, b, c->part.p, sc);                    \
-        else                                                                                   \
-            hipLaunchKernelGGL((k_spmv<GG, 1>), grid, block, 0, c->work, c->n, c->rowptr.p,    \
-                               c->col.p, c->val.p, x, y, b, c->part.p, sc);                    \
-        break;
-    switch (G) {
-        SPMV_CASE(4)
-        SPMV_CASE(8)
-        SPMV_CASE(16)
-        SPMV_CASE(32)
-        SPMV_CASE(64)
-        default: return set_error(ICCG_EINVAL, "bad SpMV lane count");
+#define SPMV_ARGS c->n, c->nslices, c->sell_off.p, c->sell_w.p, c->sell_col.p, c->sell_val.p, x, y, b, z, pnew, c->part.p, sc
+#define SPMV_W(M)                                                                              \
+    switch (c->sell_wmax) {                                                                    \
+        case 8: hipLaunchKernelGGL((k_spmv<M, 8>), grid, block, 0, c->work, SPMV_ARGS); break;   \
+        case 16: hipLaunchKernelGGL((k_spmv<M, 16>), grid, block, 0, c->work, SPMV_ARGS); break; \
+        default: hipLaunchKernelGGL((k_spmv<M, 32>), grid, block, 0, c->work, SPMV_ARGS); break; \
     }
-#undef SPMV_CASE
+    switch (mode) {
+        case SP_PLAIN: SPMV_W(SP_PLAIN) break;
+        case SP_RESID: SPMV_W(SP_RESID) break;
+        default: SPMV_W(SP_CG) break;
+    }
+#undef SPMV_W
+#undef SPMV_ARGS
     if (c->prof) c->prof->end(c->work, PK_SPMV);
     HIP_CHECK(hipGetLastError());
     return ICCG_OK;
 }
 
-SweepArgs sweep_args(const iccg_ctx *c, const DevSweep &s) {
-    SweepArgs a;
-    a.task_chunk_ptr = s.task_chunk_ptr.p;
+template <typename F>
+SweepArgs<F> sweep_args(const iccg_ctx *c, const DevSweep &s) {
+    SweepArgs<F> a;
+    a.tasks = s.tasks.p;
     a.chunks = s.chunks.p;
     a.meta = s.meta.p;
     a.scol = s.scol.p;
-    if (c->fp32()) {
+    if constexpr (sizeof(F) == 4) {
         a.sval = s.sval32.p;
         a.inv = c->inv32.p;
     } else {
@@ -589,87 +694,102 @@ SweepArgs sweep_args(const iccg_ctx *c, const DevSweep &s) {
     return a;
 }
 
-// y = L^{-1} r with r FP64; y is FP64 (y64) or FP32 (y32) by precision.
-int launch_forward(iccg_ctx *c, const double *r, void *y, const DevScalars *sc) {
-    const SweepArgs a = sweep_args(c, c->fwd);
-    for (int col = 0; col < c->ncolors; ++col) {
-        const int t0 = c->fwd.color_task_ptr[col], t1 = c->fwd.color_task_ptr[col + 1];
+// All colors of one sweep direction, one launch per color (colors ascending
+// for the forward sweep, descending for the backward sweep).
+template <typename F, bool FWD, int MODE>
+int launch_sweep_t(iccg_ctx *c, const void *in, void *out, const CgArgs &cg) {
+    using TIn = typename std::conditional<FWD, double, F>::type;
+    using TOut = typename std::conditional<FWD, F, double>::type;
+    const DevSweep &d = FWD ? c->fwd : c->bwd;
+    const SweepArgs<F> a = sweep_args<F>(c, d);
+#define SWEEP_ARGS a.tasks, a.chunks, a.meta, a.scol, a.sval, a.inv, t0, t1 - t0, pin, pout, cg
+    const TIn *pin = static_cast<const TIn *>(in);
+    TOut *pout = static_cast<TOut *>(out);
+    for (int step = 0; step < c->ncolors; ++step) {
+        const int col = FWD ? step : c->ncolors - 1 - step;
+        const int t0 = d.color_task_ptr[col], t1 = d.color_task_ptr[col + 1];
         if (t1 == t0) continue;
         if (c->prof) c->prof->begin(c->work);
-        if (c->fp32())
-            hipLaunchKernelGGL((k_sweep<float, true, double, float>), dim3(t1 - t0), dim3(64), 0,
-                               c->work, a, t0, r, static_cast<float *>(y), nullptr, nullptr, sc);
-        else
-            hipLaunchKernelGGL((k_sweep<double, true, double, double>), dim3(t1 - t0), dim3(64), 0,
-                               c->work, a, t0, r, static_cast<double *>(y), nullptr, nullptr, sc);
-        if (c->prof) c->prof->end(c->work, PK_FWD);
+        const dim3 grid(t1 - t0), block(64);
+        switch (d.kmax) {
+            case 4: hipLaunchKernelGGL((k_sweep<F, FWD, 4, MODE, TIn, TOut>), grid, block, 0, c->work, SWEEP_ARGS); break;
+            case 8: hipLaunchKernelGGL((k_sweep<F, FWD, 8, MODE, TIn, TOut>), grid, block, 0, c->work, SWEEP_ARGS); break;
+            case 16: hipLaunchKernelGGL((k_sweep<F, FWD, 16, MODE, TIn, TOut>), grid, block, 0, c->work, SWEEP_ARGS); break;
+            default: hipLaunchKernelGGL((k_sweep<F, FWD, 32, MODE, TIn, TOut>), grid, block, 0, c->work, SWEEP_ARGS); break;
+        }
+        if (c->prof) c->prof->end(c->work, FWD ? PK_FWD : PK_BWD);
     }
+#undef SWEEP_ARGS
     HIP_CHECK(hipGetLastError());
     return ICCG_OK;
 }
 
-// z = L^{-T} y; with rdot, part[task] = sum over the task's rows of rdot_i z_i.
-int launch_backward(iccg_ctx *c, const void *y, double *z, const double *rdot, double *part,
-                    const DevScalars *sc) {
-    const SweepArgs a = sweep_args(c, c->bwd);
-    for (int col = c->ncolors - 1; col >= 0; --col) {
-        const int t0 = c->bwd.color_task_ptr[col], t1 = c->bwd.color_task_ptr[col + 1];
-        if (t1 == t0) continue;
-        if (c->prof) c->prof->begin(c->work);
-        if (c->fp32())
-            hipLaunchKernelGGL((k_sweep<float, false, float, double>), dim3(t1 - t0), dim3(64), 0,
-                               c->work, a, t0, static_cast<const float *>(y), z, rdot, part, sc);
-        else
-            hipLaunchKernelGGL((k_sweep<double, false, double, double>), dim3(t1 - t0), dim3(64),
-                               0, c->work, a, t0, static_cast<const double *>(y), z, rdot, part,
-                               sc);
-        if (c->prof) c->prof->end(c->work, PK_BWD);
-    }
-    HIP_CHECK(hipGetLastError());
-    return ICCG_OK;
+template <bool FWD, int MODE>
+int launch_sweep(iccg_ctx *c, const void *in, void *out, const CgArgs &cg) {
+    return c->fp32() ? launch_sweep_t<float, FWD, MODE>(c, in, out, cg)
+                     : launch_sweep_t<double, FWD, MODE>(c, in, out, cg);
+}
+
+CgArgs no_cg() {
+    CgArgs a;
+    std::memset(&a, 0, sizeof(a));
+    return a;
 }
 
 void *ytmp(iccg_ctx *c) { return c->fp32() ? static_cast<void *>(c->y32.p) : c->y64.p; }
 
 int launch_reduce(iccg_ctx *c, int np, int op, double *out) {
-    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kVecThreads), 0, c->work, c->part.p, np,
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kReduceThreads), 0, c->work, c->part.p, np,
                        c->scal.p, op, out, c->hist.p);
     HIP_CHECK(hipGetLastError());
     return ICCG_OK;
 }
 
-// One CG iteration (all kernels return at once after the stopping test passed).
-int enqueue_iteration(iccg_ctx *c) {
+// CG iteration j (1-based; all kernels return at once after the stopping
+// test passed).  The search direction alternates between the two p buffers:
+// iteration j reads p_{j-1} from pbuf[(j+1)%2] and writes p_j to pbuf[j%2].
+//   1. SpMV:     p_j = z + beta p_{j-1}, q = A p_j, alpha = rho / (p_j, q)
+//   2. forward:  x += alpha p_j, r -= alpha q, ||r|| stopping test, y = L^{-1} r
+//   3. backward: z = L^{-T} y, beta = (r, z)/rho, rho = (r, z)
+int enqueue_iteration(iccg_ctx *c, long long j) {
     DevScalars *sc = c->scal.p;
-    ICCG_CHECK(launch_spmv(c, 0, c->p.p, c->q.p, nullptr, sc));
+    double *p_old = c->pbuf[(j + 1) & 1].p, *p_new = c->pbuf[j & 1].p;
+    ICCG_CHECK(launch_spmv(c, SP_CG, p_old, c->q.p, nullptr, c->z.p, p_new, sc));
     ICCG_CHECK(launch_reduce(c, c->spmv_blocks, OP_ALPHA, nullptr));
-    hipLaunchKernelGGL(k_update_xr, dim3(c->vec_blocks), dim3(kVecThreads), 0, c->work, c->n,
-                       c->x.p, c->r.p, c->p.p, c->q.p, sc, c->part.p);
-    HIP_CHECK(hipGetLastError());
-    ICCG_CHECK(launch_reduce(c, c->vec_blocks, OP_RR, nullptr));
-    ICCG_CHECK(launch_forward(c, c->r.p, ytmp(c), sc));
-    ICCG_CHECK(launch_backward(c, ytmp(c), c->z.p, c->r.p, c->part.p, sc));
+    CgArgs f = no_cg();
+    f.x = c->x.p;
+    f.r = c->r.p;
+    f.p = p_new;
+    f.q = c->q.p;
+    f.part = c->part.p;
+    f.sc = sc;
+    ICCG_CHECK((launch_sweep<true, SW_CG_FWD>(c, nullptr, ytmp(c), f)));
+    ICCG_CHECK(launch_reduce(c, c->fwd.ntasks, OP_RR, nullptr));
+    CgArgs g = no_cg();
+    g.rdot = c->r.p;
+    g.part = c->part.p;
+    g.sc = sc;
+    ICCG_CHECK((launch_sweep<false, SW_DOT_BWD>(c, ytmp(c), c->z.p, g)));
     ICCG_CHECK(launch_reduce(c, c->bwd.ntasks, OP_BETA, nullptr));
-    hipLaunchKernelGGL(k_update_p, dim3(c->vec_blocks), dim3(kVecThreads), 0, c->work, c->n,
-                       c->p.p, c->z.p, sc);
-    HIP_CHECK(hipGetLastError());
     return ICCG_OK;
 }
 
-int enqueue_batch(iccg_ctx *c, int iters) {
-    for (int k = 0; k < iters; ++k) ICCG_CHECK(enqueue_iteration(c));
+// Batches start at odd iteration numbers and hold an even number of
+// iterations, so one captured graph serves every batch.
+int enqueue_batch(iccg_ctx *c, long long j0, int iters) {
+    for (int k = 0; k < iters; ++k) ICCG_CHECK(enqueue_iteration(c, j0 + k));
     return ICCG_OK;
 }
 
-int run_batch(iccg_ctx *c, int iters) {
-    if (!c->opt.use_graph) return enqueue_batch(c, iters);
+int run_batch(iccg_ctx *c, long long j0, int iters) {
+    if (!c->opt.use_graph) return enqueue_batch(c, j0, iters);
     if (!c->graph || c->graph_iters != iters) {
         if (c->graph) {
             HIP_CHECK(hipGraphExecDestroy(c->graph));
             c->graph = nullptr;
         }
         HIP_CHECK(hipStreamBeginCapture(c->work, hipStreamCaptureModeThreadLocal));
-        int st = enqueue_batch(c, iters);
+        int st = enqueue_batch(c, 1, iters);
         hipGraph_t g = nullptr;
         hipError_t e = hipStreamEndCapture(c->work, &g);
         if (st != ICCG_OK) {
@@ -718,8 +838,10 @@ int upload_sweep(iccg_ctx *c, const SweepPlan &plan, DevSweep &d) {
     d.ntasks = static_cast<int>(plan.task_chunk_ptr.size()) - 1;
     d.nslots = static_cast<long long>(plan.slot_col.size());
     d.max_depth = plan.max_depth;
+    d.max_width = plan.max_width;
+    d.kmax = plan.max_width <= 4 ? 4 : plan.max_width <= 8 ? 8 : plan.max_width <= 16 ? 16 : 32;
     d.color_task_ptr = plan.color_task_ptr;
-    ICCG_CHECK(d.task_chunk_ptr.upload(plan.task_chunk_ptr.data(), plan.task_chunk_ptr.size(), c->work));
+    ICCG_CHECK(d.tasks.upload(plan.tasks.data(), plan.tasks.size(), c->work));
     ICCG_CHECK(d.chunks.upload(plan.chunks.data(), plan.chunks.size(), c->work));
     ICCG_CHECK(d.meta.upload(plan.meta.data(), plan.meta.size(), c->work));
     ICCG_CHECK(d.scol.upload(plan.slot_col.data(), plan.slot_col.size(), c->work));
@@ -731,6 +853,7 @@ int upload_sweep(iccg_ctx *c, const SweepPlan &plan, DevSweep &d) {
 struct HostSetup {
     std::vector<int> dpos, tpos;
     SweepPlan fwd, bwd;
+    SellMatrix sell;
     int max_block = 0;
 };
 
@@ -791,6 +914,7 @@ int validate(int n, const int *rowptr, const int *col, const double *val, int nb
                                 color_ptr, pack_rows, hs.fwd));
     ICCG_CHECK(build_sweep_plan(false, n, rowptr, col, tpos.data(), nblocks, block_ptr, ncolors,
                                 color_ptr, pack_rows, hs.bwd));
+    ICCG_CHECK(build_sell(n, rowptr, col, val, hs.sell));
     return ICCG_OK;
 }
 
@@ -823,16 +947,21 @@ int upload_setup(iccg_ctx *c, int n, const int *rowptr, const int *col, const do
         ICCG_CHECK(c->inv64.alloc(n));
     }
     ICCG_CHECK(c->y64.alloc(n));
-    for (DevArray<double> *v : {&c->x, &c->r, &c->z, &c->p, &c->q, &c->b}) ICCG_CHECK(v->alloc(n));
+    for (DevArray<double> *v : {&c->x, &c->r, &c->z, &c->q, &c->b, &c->pbuf[0], &c->pbuf[1]})
+        ICCG_CHECK(v->alloc(n));
 
-    // SpMV: lanes per row = power of two near the mean row length
-    const double mean = static_cast<double>(nnz) / n;
-    int G = 4;
-    while (G < 64 && G < mean * 0.75) G *= 2;
-    c->spmv_lanes = G;
-    const int rows_per_block = kVecThreads / G;
-    c->spmv_blocks = grid_for(n, rows_per_block, 8192);
-    c->vec_blocks = grid_for(n, kVecThreads, kMaxVecBlocks);
+    c->nslices = static_cast<int>(hs.sell.slice_off.size());
+    ICCG_CHECK(c->sell_off.upload(hs.sell.slice_off.data(), hs.sell.slice_off.size(), s));
+    ICCG_CHECK(c->sell_w.upload(hs.sell.slice_width.data(), hs.sell.slice_width.size(), s));
+    ICCG_CHECK(c->sell_col.upload(hs.sell.col.data(), hs.sell.col.size(), s));
+    ICCG_CHECK(c->sell_val.upload(hs.sell.val.data(), hs.sell.val.size(), s));
+    // grids are multiples of 8 so the XCD remap spreads whole ranges
+    auto round8 = [](int g) { return std::max(8, (g + 7) / 8 * 8); };
+    int wmax = 0;
+    for (int w : hs.sell.slice_width) wmax = std::max(wmax, w);
+    c->sell_wmax = wmax <= 8 ? 8 : wmax <= 16 ? 16 : 32;
+    c->spmv_blocks = round8(grid_for(c->nslices, 1, 8192));
+    c->vec_blocks = round8(grid_for(n, kVecThreads, kMaxVecBlocks));
     const int np = std::max({c->spmv_blocks, c->vec_blocks, c->bwd.ntasks, c->fwd.ntasks, 1});
     ICCG_CHECK(c->part.alloc(np));
     ICCG_CHECK(c->scal.alloc(1));
@@ -882,29 +1011,36 @@ int solve_impl(iccg_ctx *c, const double *b, double *x, double tol, int maxit, i
     HIP_CHECK(hipGetLastError());
     ICCG_CHECK(enqueue_dot(c, c->b.p, c->b.p, OP_BNORM, nullptr));
     // r = b - A x, stopping test on the initial residual
-    ICCG_CHECK(launch_spmv(c, 1, c->x.p, c->r.p, c->b.p, nullptr));
+    ICCG_CHECK(launch_spmv(c, SP_RESID, c->x.p, c->r.p, c->b.p, nullptr, nullptr, nullptr));
     ICCG_CHECK(launch_reduce(c, c->spmv_blocks, OP_INIT_RR, nullptr));
-    // z = M^{-1} r, rho = (r, z), p = z
-    ICCG_CHECK(launch_forward(c, c->r.p, ytmp(c), c->scal.p));
-    ICCG_CHECK(launch_backward(c, ytmp(c), c->z.p, c->r.p, c->part.p, c->scal.p));
+    // z = M^{-1} r, rho = (r, z); p_0 = 0 and beta = 0 make the first SpMV form p_1 = z
+    CgArgs init = no_cg();
+    init.sc = c->scal.p;
+    ICCG_CHECK((launch_sweep<true, SW_APPLY>(c, c->r.p, ytmp(c), init)));
+    init.rdot = c->r.p;
+    init.part = c->part.p;
+    ICCG_CHECK((launch_sweep<false, SW_DOT_BWD>(c, ytmp(c), c->z.p, init)));
     ICCG_CHECK(launch_reduce(c, c->bwd.ntasks, OP_RHO, nullptr));
-    hipLaunchKernelGGL(k_copy, dim3(c->vec_blocks), dim3(kVecThreads), 0, s, n, c->p.p, c->z.p, c->scal.p);
+    hipLaunchKernelGGL(k_fill, dim3(c->vec_blocks), dim3(kVecThreads), 0, s, n, c->pbuf[0].p, 0.0);
     HIP_CHECK(hipGetLastError());
     ICCG_CHECK(read_scalars(c));
-    const int batch = std::max(1, c->opt.check_every);
+    const int batch = std::max(2, (c->opt.check_every + 1) / 2 * 2);
+    long long j = 1;
     while (c->h_scal->done == DONE_RUNNING) {
         if (c->prof) {
             // instrumented: one eager iteration at a time, events harvested
-            ICCG_CHECK(enqueue_iteration(c));
+            ICCG_CHECK(enqueue_iteration(c, j));
+            j += 1;
             ICCG_CHECK(read_scalars(c));
             c->prof->harvest();
         } else {
-            ICCG_CHECK(run_batch(c, batch));
+            ICCG_CHECK(run_batch(c, j, batch));
+            j += batch;
             ICCG_CHECK(read_scalars(c));
         }
     }
     // true residual
-    ICCG_CHECK(launch_spmv(c, 1, c->x.p, c->q.p, c->b.p, nullptr));
+    ICCG_CHECK(launch_spmv(c, SP_RESID, c->x.p, c->q.p, c->b.p, nullptr, nullptr, nullptr));
     ICCG_CHECK(launch_reduce(c, c->spmv_blocks, OP_TRUE, nullptr));
     HIP_CHECK(hipMemcpyAsync(x, c->x.p, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
     HIP_CHECK(hipEventRecord(c->ev_t1, s));
@@ -1065,8 +1201,8 @@ int ic_apply(iccg_ctx *c, const double *r, double *z) {
         if (!r || !z) return set_error(ICCG_EINVAL, "null vector");
         if (r == z) return set_error(ICCG_EINVAL, "r and z must not alias");
         if (!c->has_factor) return set_error(ICCG_ESTATE, "no factor");
-        ICCG_CHECK(launch_forward(c, r, ytmp(c), nullptr));
-        return launch_backward(c, ytmp(c), z, nullptr, nullptr, nullptr);
+        ICCG_CHECK((launch_sweep<true, SW_APPLY>(c, r, ytmp(c), no_cg())));
+        return launch_sweep<false, SW_APPLY>(c, ytmp(c), z, no_cg());
     });
 }
 
@@ -1075,14 +1211,14 @@ int ic_forward(iccg_ctx *c, const double *r, double *y) {
         if (!r || !y) return set_error(ICCG_EINVAL, "null vector");
         if (!c->has_factor) return set_error(ICCG_ESTATE, "no factor");
         if (c->fp32()) {
-            ICCG_CHECK(launch_forward(c, r, c->y32.p, nullptr));
+            ICCG_CHECK((launch_sweep<true, SW_APPLY>(c, r, c->y32.p, no_cg())));
             hipLaunchKernelGGL((k_convert<double, float>), dim3(c->vec_blocks), dim3(kVecThreads), 0,
                                c->work, c->n, y, c->y32.p);
             HIP_CHECK(hipGetLastError());
             return ICCG_OK;
         }
         if (r == y) return set_error(ICCG_EINVAL, "r and y must not alias");
-        return launch_forward(c, r, y, nullptr);
+        return launch_sweep<true, SW_APPLY>(c, r, y, no_cg());
     });
 }
 
@@ -1095,16 +1231,16 @@ int ic_backward(iccg_ctx *c, const double *y, double *z) {
             hipLaunchKernelGGL((k_convert<float, double>), dim3(c->vec_blocks), dim3(kVecThreads), 0,
                                c->work, c->n, c->y32.p, y);
             HIP_CHECK(hipGetLastError());
-            return launch_backward(c, c->y32.p, z, nullptr, nullptr, nullptr);
+            return launch_sweep<false, SW_APPLY>(c, c->y32.p, z, no_cg());
         }
-        return launch_backward(c, y, z, nullptr, nullptr, nullptr);
+        return launch_sweep<false, SW_APPLY>(c, y, z, no_cg());
     });
 }
 
 int iccg_spmv(iccg_ctx *c, const double *p, double *q, double *pq_host) {
     return entry(c, [&]() -> int {
         if (!p || !q || p == q) return set_error(ICCG_EINVAL, "need distinct p and q");
-        ICCG_CHECK(launch_spmv(c, 0, p, q, nullptr, nullptr));
+        ICCG_CHECK(launch_spmv(c, SP_PLAIN, p, q, nullptr, nullptr, nullptr, nullptr));
         if (pq_host) {
             ICCG_CHECK(launch_reduce(c, c->spmv_blocks, OP_STORE, c->b.p));
             HIP_CHECK(hipMemcpyAsync(pq_host, c->b.p, sizeof(double), hipMemcpyDeviceToHost, c->work));

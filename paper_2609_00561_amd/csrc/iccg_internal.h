@@ -24,12 +24,23 @@ constexpr int kChunkRows = 64;
 struct Chunk {
     int32_t row0;    // first row (permuted numbering)
     int32_t off;     // first slot of this chunk
-    int16_t nrows;   // 1..64
-    int16_t width;   // max entries of a row in this chunk
-    int16_t depth;   // number of intra-chunk levels (>= 1)
-    int16_t pad;
+    int32_t shape;   // nrows (1..64) | width << 16 (max entries of a row)
+    int32_t depth;   // number of intra-chunk levels (>= 1)
+    int nrows() const { return shape & 0xffff; }
+    int width() const { return shape >> 16; }
 };
 static_assert(sizeof(Chunk) == 16, "Chunk layout");
+
+// One wavefront task: its first chunk in processing order (forward: lowest,
+// backward: highest) inline, so a task starts from a single 32-byte load, and
+// the range [c0, c1) of all its chunks.
+struct TaskRec {
+    Chunk first;
+    int32_t c0, c1;
+    int32_t nchunks;
+    int32_t pad;
+};
+static_assert(sizeof(TaskRec) == 32, "TaskRec layout");
 
 // Per-row schedule word: number of entries whose value is final before the
 // chunk starts (bits 0..15), number of entries inside the chunk (bits
@@ -47,12 +58,23 @@ struct SweepPlan {
     bool forward = true;
     std::vector<int> color_task_ptr;   // ncolors+1, tasks of each color
     std::vector<int> task_chunk_ptr;   // ntasks+1
+    std::vector<TaskRec> tasks;        // ntasks
     std::vector<Chunk> chunks;
     std::vector<uint32_t> meta;        // n
     std::vector<int> slot_col;         // column per slot, -1 for padding
     std::vector<int> slot_src;         // CSR position of the factor value, -1 for padding
     int max_depth = 0;
+    int max_width = 0;
 };
+
+// Sliced ELL copy of A' for the SpMV: slices of 64 consecutive rows; entry k
+// of the slice's row t at slice_off[s] + k*64 + t (column -1, value 0 pads).
+struct SellMatrix {
+    std::vector<int> slice_off, slice_width;   // nslices
+    std::vector<int> col;
+    std::vector<double> val;
+};
+int build_sell(int n, const int *rowptr, const int *col, const double *val, SellMatrix &out);
 
 // Builds both sweep plans from the validated permuted pattern.  tpos[k] is
 // the CSR position of the transpose of entry k.

@@ -98,12 +98,12 @@ int build_sweep_plan(bool forward, int n, const int *rowptr, const int *col, con
         Chunk ch;
         ch.row0 = r0;
         ch.off = static_cast<int32_t>(nslots);
-        ch.nrows = static_cast<int16_t>(nr);
-        ch.width = static_cast<int16_t>(width);
-        ch.depth = static_cast<int16_t>(depth);
-        ch.pad = 0;
+        if (width > 0x7fff) return set_error(ICCG_EINVAL, "a row has more than 32767 entries in one triangle");
+        ch.shape = nr | (width << 16);
+        ch.depth = depth;
         out.chunks.push_back(ch);
         out.max_depth = std::max(out.max_depth, depth);
+        out.max_width = std::max(out.max_width, width);
         out.slot_col.resize(nslots + static_cast<long long>(width) * nr, -1);
         out.slot_src.resize(nslots + static_cast<long long>(width) * nr, -1);
         for (int t = 0; t < nr; ++t) {
@@ -118,6 +118,44 @@ int build_sweep_plan(bool forward, int n, const int *rowptr, const int *col, con
         }
         nslots += static_cast<long long>(width) * nr;
     }
+    const int ntasks = static_cast<int>(out.task_chunk_ptr.size()) - 1;
+    out.tasks.resize(ntasks);
+    for (int t = 0; t < ntasks; ++t) {
+        TaskRec &tr = out.tasks[t];
+        tr.c0 = out.task_chunk_ptr[t];
+        tr.c1 = out.task_chunk_ptr[t + 1];
+        tr.nchunks = tr.c1 - tr.c0;
+        tr.pad = 0;
+        tr.first = out.chunks[forward ? tr.c0 : tr.c1 - 1];
+    }
+    return ICCG_OK;
+}
+
+int build_sell(int n, const int *rowptr, const int *col, const double *val, SellMatrix &out) {
+    const int ns = (n + kChunkRows - 1) / kChunkRows;
+    out.slice_off.assign(ns, 0);
+    out.slice_width.assign(ns, 0);
+    long long total = 0;
+    for (int s = 0; s < ns; ++s) {
+        int w = 0;
+        for (int i = s * kChunkRows; i < std::min(n, (s + 1) * kChunkRows); ++i)
+            w = std::max(w, rowptr[i + 1] - rowptr[i]);
+        out.slice_off[s] = static_cast<int>(total);
+        out.slice_width[s] = w;
+        total += static_cast<long long>(w) * kChunkRows;
+        if (total >= (1LL << 31)) return set_error(ICCG_EINVAL, "sliced ELL copy exceeds 2^31 slots");
+    }
+    out.col.assign(total, -1);
+    out.val.assign(total, 0.0);
+    for (int s = 0; s < ns; ++s)
+        for (int i = s * kChunkRows; i < std::min(n, (s + 1) * kChunkRows); ++i) {
+            const int t = i - s * kChunkRows;
+            for (int k = rowptr[i]; k < rowptr[i + 1]; ++k) {
+                const long long slot = out.slice_off[s] + static_cast<long long>(k - rowptr[i]) * kChunkRows + t;
+                out.col[slot] = col[k];
+                out.val[slot] = val[k];
+            }
+        }
     return ICCG_OK;
 }
 

@@ -8,7 +8,9 @@ Tolerances:
 * SpMV: 1e-14 relative per entry scale; dot products 1e-13 relative.
 * Solve: relres <= tol, iteration count within max(2, 1%) of the oracle's,
   residual histories within 1e-6 relative over the first 20 iterations and
-  1e-2 over the first 50 (rounding noise grows with the condition number).
+  1e-2 over the first 50 while the residual is above 1e-6 of its peak
+  (rounding noise grows with the condition number and with transient residual
+  growth).
 """
 import numpy as np
 import pytest
@@ -186,7 +188,8 @@ def test_solve_parity(case):
     m = min(20, ref.iters, res["iters"]) + 1
     assert np.allclose(hist[:m], ref.history[:m], rtol=1e-6, atol=0)
     m = min(50, ref.iters, res["iters"]) + 1
-    assert np.allclose(hist[:m], ref.history[:m], rtol=1e-2, atol=0)
+    above = ref.history[:m] >= 1e-6 * np.max(ref.history)
+    assert np.allclose(hist[:m][above], ref.history[:m][above], rtol=1e-2, atol=0)
     err = np.linalg.norm(x - ref.x) / np.linalg.norm(ref.x)
     print(case, "iters", res["iters"], ref.iters, "x rel diff", err)
     # the two iterates both satisfy relres <= 1e-8; their distance is bounded
@@ -240,8 +243,9 @@ def test_solve_edge_cases():
         # NaN in b
         b = cs[6].copy()
         b[10] = np.nan
-        res = ctx.solve(_dev(b), torch.zeros_like(xd), raise_on_noconv=False)
-        assert res["status"] == iccg.ICCG_ENAN
+        with pytest.raises(iccg.IccgError) as e:
+            ctx.solve(_dev(b), torch.zeros_like(xd), raise_on_noconv=False)
+        assert e.value.status == iccg.ICCG_ENAN
         # warm start from the solution: converges at once
         xs = torch.zeros_like(xd)
         ctx.solve(_dev(cs[6]), xs, tol=1e-10)
