@@ -344,3 +344,20 @@ def banded_graph(n: int, width: int) -> CSR:
     lo = np.concatenate([a, b])
     hi = np.concatenate([a + 1, b + width])
     return _edge_matrix(n, lo, hi, np.ones(lo.size), 1.0)
+
+
+def glorot_params(shapes, seed: int, zero=("b", "bm", "br", "wo", "bo")) -> np.ndarray:
+    """Concatenated parameter vector: every matrix U(-a, a) with
+    a = sqrt(6 / (fan_in + fan_out)), every block whose name is in zero set to 0.
+    shapes: list of (name, shape) in layout order."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for name, shp in shapes:
+        size = int(np.prod(shp))
+        if name in zero:
+            parts.append(np.zeros(size))
+        else:
+            fan_out, fan_in = shp[0], (shp[1] if len(shp) > 1 else 1)
+            a = np.sqrt(6.0 / (fan_in + fan_out))
+            parts.append(rng.uniform(-a, a, size))
+    return np.concatenate(parts)
