@@ -145,6 +145,10 @@ int ic0_factor(iccg_ctx *c, int *breakdown_row);
  */
 int iccg_set_factor(iccg_ctx *c, const double *lvals_dev, int *bad_row);
 
+/* Reinstall the IC(0) factor computed by ic0_factor (the learned form's
+ * fallback).  ICCG_ESTATE if ic0_factor has not succeeded on this context. */
+int iccg_restore_ic0(iccg_ctx *c);
+
 /* Copy the current factor (A' CSR positions, upper part zero) to host lvals[nnz]. */
 int iccg_get_factor(iccg_ctx *c, double *lvals);
 
@@ -210,6 +214,51 @@ typedef struct {
 } iccg_info;
 
 int iccg_get_info(iccg_ctx *c, iccg_info *info);
+
+/* ------------------------------------------------------------------------ */
+/* Learned factor form                                                       */
+/* ------------------------------------------------------------------------ */
+/*
+ * A message-passing network that predicts corrections to the IC(0) factor
+ * values on the same pattern; the sweeps are unchanged.  (The paper has no
+ * learned component; this is the added learned-factor form.)  In the scaled
+ * space s_i = 1/sqrt(a'_ii), A~ = S A' S, L~0 = S L0:
+ *   node features [L~0_ii, sum_{j!=i}|A~_ij|, deg_i/26];
+ *   edge features [A~_ij, j<i, j==i, L~0 at the lower position of (i,j)];
+ *   3 layers, width 32: h_i <- relu(W_s h_i + b + sum_{j!=i} relu(W_m [h_j; f_ij] + b_m));
+ *   readout on lower entries (i,j), j<=i: d = w_o . relu(W_r [h_i; h_j; f_ij] + b_r) + b_o;
+ *   factor L_ij = L0_ij + 0.1 d / s_i (so w_o = 0, b_o = 0 reproduces IC(0) exactly);
+ *   training loss: mean over probes z of ||L~ L~^T z - A~ z||^2 / ||A~ z||^2.
+ * Parameters (FP32, iccg_mpnn_param_count() of them): per layer W_s[32][d], b[32],
+ * W_m[32][d+4], b_m[32] with d = 3, 32, 32; then W_r[32][68], b_r[32], w_o[32],
+ * b_o; matrices row-major.  Contexts used with a network need ic0_factor first.
+ */
+typedef struct iccg_mpnn iccg_mpnn;
+
+int  iccg_mpnn_param_count(void);
+/* params: host FP32 array of iccg_mpnn_param_count(); stream: hipStream_t or NULL */
+int  iccg_mpnn_create(iccg_mpnn **out, const float *params, void *stream);
+int  iccg_mpnn_get_params(iccg_mpnn *m, float *params);
+/* replaces the parameters and resets the Adam state */
+int  iccg_mpnn_set_params(iccg_mpnn *m, const float *params);
+/*
+ * Probe loss and its gradient for the matrix of context c (FP32 forward and
+ * backward kernels).  probes: DEVICE FP64 [nprobes][n] (row-major, one probe
+ * per row, drawn by the caller).  *loss (host, may be NULL); grad: host FP32
+ * array of param_count (may be NULL).
+ */
+int  iccg_mpnn_loss_grad(iccg_mpnn *m, iccg_ctx *c, const double *probes, int nprobes,
+                         double *loss, float *grad);
+/* One training step: loss, gradient and an Adam update (beta1 0.9, beta2 0.999,
+ * eps 1e-8, bias corrected) with learning rate lr.  *loss may be NULL (then the
+ * call does not synchronize). */
+int  iccg_mpnn_train_step(iccg_mpnn *m, iccg_ctx *c, const double *probes, int nprobes,
+                          float lr, double *loss);
+/* Inference: the predicted factor of A' into DEVICE lvals[nnz] (A' CSR positions,
+ * upper part 0), ready for iccg_set_factor.  bf16 = 1 stores weights and
+ * activations in BF16 (FP32 accumulation); 0 runs in FP32. */
+int  iccg_mpnn_predict(iccg_mpnn *m, iccg_ctx *c, int bf16, double *lvals);
+void iccg_mpnn_destroy(iccg_mpnn *m);
 
 const char *iccg_strerror(int status);
 const char *iccg_last_error(void);

@@ -20,7 +20,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libiccg.so")
 
 HOST_SOURCES = ["order.cpp", "setup.cpp"]
-HIP_SOURCES = ["iccg.hip"]
+HIP_SOURCES = ["iccg.hip", "mpnn.hip"]
 ARCH = os.environ.get("ICCG_OFFLOAD_ARCH", "gfx950")
 
 

@@ -22,7 +22,7 @@
 // graph) with a single host read of the flag per batch.
 #include <hip/hip_runtime.h>
 
-#include "iccg_internal.h"
+#include "iccg_device.h"
 
 #include <algorithm>
 #include <climits>
@@ -46,38 +46,6 @@ int set_error(int code, const std::string &msg) {
 }  // namespace iccg
 
 using namespace iccg;
-
-#define HIP_CHECK(expr)                                                                    \
-    do {                                                                                   \
-        hipError_t e_ = (expr);                                                            \
-        if (e_ != hipSuccess)                                                              \
-            return set_error(e_ == hipErrorOutOfMemory ? ICCG_ENOMEM : ICCG_EHIP,          \
-                             std::string(#expr) + ": " + hipGetErrorString(e_));           \
-    } while (0)
-
-#define ICCG_CHECK(expr)             \
-    do {                             \
-        int st_ = (expr);            \
-        if (st_ != ICCG_OK) return st_; \
-    } while (0)
-
-// ---------------------------------------------------------------------------
-// device scalars of one CG solve
-// ---------------------------------------------------------------------------
-enum : int { DONE_RUNNING = 0, DONE_CONVERGED = 1, DONE_NAN = 2, DONE_MAXIT = 3 };
-
-struct DevScalars {
-    double rho;       // (r, z)
-    double alpha, beta;
-    double bnorm;     // ||b||
-    double relres;    // ||r||/||b|| after the last update
-    double relres_true;
-    double tol;
-    int iter;         // completed iterations
-    int done;
-    int maxit;
-    int hist_cap;
-};
 
 enum ReduceOp : int {
     OP_STORE = 0,    // out[0] = sum
@@ -494,157 +462,6 @@ __global__ __launch_bounds__(64) void k_sweep(const TaskRec *__restrict__ tasks,
     }
 }
 
-// ---------------------------------------------------------------------------
-// context
-// ---------------------------------------------------------------------------
-template <typename T>
-struct DevArray {
-    T *p = nullptr;
-    size_t count = 0;
-    DevArray() = default;
-    DevArray(const DevArray &) = delete;
-    DevArray &operator=(const DevArray &) = delete;
-    ~DevArray() { release(); }
-    void release() {
-        if (p) (void)hipFree(p);
-        p = nullptr;
-        count = 0;
-    }
-    int alloc(size_t c) {
-        release();
-        if (c == 0) c = 1;
-        hipError_t e = hipMalloc(&p, c * sizeof(T));
-        if (e != hipSuccess) {
-            p = nullptr;
-            return set_error(ICCG_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
-        }
-        count = c;
-        return ICCG_OK;
-    }
-    int upload(const T *h, size_t c, hipStream_t s) {
-        ICCG_CHECK(alloc(c));
-        if (c) HIP_CHECK(hipMemcpyAsync(p, h, c * sizeof(T), hipMemcpyHostToDevice, s));
-        return ICCG_OK;
-    }
-};
-
-struct DevSweep {
-    int ntasks = 0;
-    long long nslots = 0;
-    int max_depth = 0;
-    int max_width = 0;
-    int kmax = 4;                      // register slots per row in k_sweep
-    std::vector<int> color_task_ptr;
-    DevArray<TaskRec> tasks;
-    DevArray<Chunk> chunks;
-    DevArray<uint32_t> meta;
-    DevArray<int> scol, ssrc;
-    DevArray<double> sval64;
-    DevArray<float> sval32;
-};
-
-// Per-launch HIP-event timing of an instrumented (eager) solve.
-enum ProfKind : int { PK_SPMV = 0, PK_FWD = 1, PK_BWD = 2, PK_COUNT = 3 };
-
-struct Profiler {
-    std::vector<hipEvent_t> pool;
-    std::vector<int> kinds;       // kind of each recorded pair
-    size_t used = 0;              // events used in the current round
-    double ms[PK_COUNT] = {0, 0, 0};
-    long long launches[PK_COUNT] = {0, 0, 0};
-    ~Profiler() {
-        for (hipEvent_t e : pool) (void)hipEventDestroy(e);
-    }
-    hipEvent_t next() {
-        if (used == pool.size()) {
-            hipEvent_t e = nullptr;
-            if (hipEventCreate(&e) != hipSuccess) return nullptr;
-            pool.push_back(e);
-        }
-        return pool[used++];
-    }
-    void begin(hipStream_t s) {
-        hipEvent_t e = next();
-        if (e) (void)hipEventRecord(e, s);
-    }
-    void end(hipStream_t s, int kind) {
-        hipEvent_t e = next();
-        if (e) (void)hipEventRecord(e, s);
-        kinds.push_back(kind);
-    }
-    // after the stream has drained: fold the recorded pairs into the totals
-    void harvest() {
-        for (size_t k = 0; k < kinds.size() && 2 * k + 1 < used; ++k) {
-            float t = 0.0f;
-            if (hipEventElapsedTime(&t, pool[2 * k], pool[2 * k + 1]) == hipSuccess) {
-                ms[kinds[k]] += t;
-                launches[kinds[k]] += 1;
-            }
-        }
-        kinds.clear();
-        used = 0;
-    }
-};
-
-struct iccg_ctx {
-    Profiler *prof = nullptr;     // set only during iccg_profile_solve
-    int n = 0, nnz = 0, nnz_lower = 0, nblocks = 0, ncolors = 0, max_block = 0;
-    iccg_options opt{};
-    hipStream_t user = nullptr;   // caller's stream
-    hipStream_t work = nullptr;   // internal stream (graph capture needs a non-null stream)
-    hipEvent_t ev_in = nullptr, ev_out = nullptr, ev_t0 = nullptr, ev_t1 = nullptr;
-    std::vector<int> h_rowptr, h_col, h_dpos;
-    std::vector<double> h_val;
-    DevArray<int> rowptr, col, dpos;
-    DevArray<double> val, lval, lstage;
-    DevSweep fwd, bwd;
-    DevArray<double> inv64;
-    DevArray<float> inv32;
-    bool has_factor = false;
-    DevArray<double> x, r, z, q, b, y64;
-    DevArray<double> pbuf[2];       // search direction, double buffered across iterations
-    DevArray<float> y32;
-    DevArray<double> part, hist;
-    DevArray<DevScalars> scal;
-    DevArray<int> dint;
-    DevScalars *h_scal = nullptr;   // pinned
-    int nslices = 0;                // sliced ELL copy of A' for the SpMV
-    int sell_wmax = 8;              // register slots per row in k_spmv
-    DevArray<int> sell_off, sell_w, sell_col;
-    DevArray<double> sell_val;
-    int spmv_blocks = 1, vec_blocks = 1;
-    hipGraphExec_t graph = nullptr;
-    int graph_iters = 0;
-    double last_ms = 0.0;
-    int last_iters = 0;
-    int last_hist = 0;
-
-    ~iccg_ctx() {
-        if (graph) (void)hipGraphExecDestroy(graph);
-        if (h_scal) (void)hipHostFree(h_scal);
-        if (ev_in) (void)hipEventDestroy(ev_in);
-        if (ev_out) (void)hipEventDestroy(ev_out);
-        if (ev_t0) (void)hipEventDestroy(ev_t0);
-        if (ev_t1) (void)hipEventDestroy(ev_t1);
-        if (work) (void)hipStreamDestroy(work);
-    }
-
-    bool fp32() const { return opt.precision == ICCG_FP32; }
-
-    // make the internal stream wait for the caller's stream
-    int enter() {
-        HIP_CHECK(hipEventRecord(ev_in, user));
-        HIP_CHECK(hipStreamWaitEvent(work, ev_in, 0));
-        return ICCG_OK;
-    }
-    // make the caller's stream wait for the internal stream
-    int leave() {
-        HIP_CHECK(hipEventRecord(ev_out, work));
-        HIP_CHECK(hipStreamWaitEvent(user, ev_out, 0));
-        return ICCG_OK;
-    }
-};
-
 namespace {
 
 int grid_for(long long items, int threads, int cap) {
@@ -937,6 +754,7 @@ int upload_setup(iccg_ctx *c, int n, const int *rowptr, const int *col, const do
     ICCG_CHECK(c->col.upload(col, nnz, s));
     ICCG_CHECK(c->val.upload(val, nnz, s));
     ICCG_CHECK(c->dpos.upload(hs.dpos.data(), n, s));
+    ICCG_CHECK(c->tpos.upload(hs.tpos.data(), nnz, s));
     ICCG_CHECK(upload_sweep(c, hs.fwd, c->fwd));
     ICCG_CHECK(upload_sweep(c, hs.bwd, c->bwd));
     ICCG_CHECK(c->lval.alloc(nnz));
@@ -1157,6 +975,9 @@ int ic0_factor(iccg_ctx *c, int *breakdown_row) {
             return set_error(ICCG_EBREAKDOWN, "IC(0) pivot not positive at row " + std::to_string(row));
         }
         HIP_CHECK(hipMemcpyAsync(c->lval.p, lv.data(), sizeof(double) * lv.size(), hipMemcpyHostToDevice, c->work));
+        if (!c->lval0.p) ICCG_CHECK(c->lval0.alloc(c->nnz));
+        HIP_CHECK(hipMemcpyAsync(c->lval0.p, lv.data(), sizeof(double) * lv.size(), hipMemcpyHostToDevice, c->work));
+        c->has_ic0 = true;
         ICCG_CHECK(install_factor(c));
         HIP_CHECK(hipStreamSynchronize(c->work));   // lv is released on return
         return ICCG_OK;
@@ -1182,6 +1003,14 @@ int iccg_set_factor(iccg_ctx *c, const double *lvals_dev, int *bad_row) {
             return set_error(ICCG_EBREAKDOWN, "factor rejected at row " + std::to_string(bad));
         }
         HIP_CHECK(hipMemcpyAsync(c->lval.p, c->lstage.p, sizeof(double) * c->nnz, hipMemcpyDeviceToDevice, c->work));
+        return install_factor(c);
+    });
+}
+
+int iccg_restore_ic0(iccg_ctx *c) {
+    return entry(c, [&]() -> int {
+        if (!c->has_ic0) return set_error(ICCG_ESTATE, "no IC(0) factor: call ic0_factor first");
+        HIP_CHECK(hipMemcpyAsync(c->lval.p, c->lval0.p, sizeof(double) * c->nnz, hipMemcpyDeviceToDevice, c->work));
         return install_factor(c);
     });
 }

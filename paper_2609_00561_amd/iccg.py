@@ -37,10 +37,12 @@ QUALITY = {"modularity": 0, "cpm": 1}
 # every symbol the header declares
 EXPORTS = [
     "iccg_default_options", "iccg_order_abmc", "iccg_order_leiden", "iccg_permute",
-    "iccg_setup", "ic0_factor", "iccg_set_factor", "iccg_get_factor", "ic_apply",
+    "iccg_setup", "ic0_factor", "iccg_set_factor", "iccg_restore_ic0", "iccg_get_factor", "ic_apply",
     "ic_forward", "ic_backward", "iccg_spmv", "iccg_dot", "iccg_solve",
     "iccg_residual_history", "iccg_profile_solve", "iccg_get_info", "iccg_strerror", "iccg_last_error",
-    "iccg_destroy",
+    "iccg_destroy", "iccg_mpnn_param_count", "iccg_mpnn_create", "iccg_mpnn_get_params",
+    "iccg_mpnn_set_params", "iccg_mpnn_loss_grad", "iccg_mpnn_train_step", "iccg_mpnn_predict",
+    "iccg_mpnn_destroy",
 ]
 
 
@@ -90,6 +92,15 @@ def load():
         "ic0_factor": (i, [vp, ip]),
         "iccg_set_factor": (i, [vp, vp, ip]),
         "iccg_get_factor": (i, [vp, vp]),
+        "iccg_restore_ic0": (i, [vp]),
+        "iccg_mpnn_param_count": (i, []),
+        "iccg_mpnn_create": (i, [ctypes.POINTER(vp), vp, vp]),
+        "iccg_mpnn_get_params": (i, [vp, vp]),
+        "iccg_mpnn_set_params": (i, [vp, vp]),
+        "iccg_mpnn_loss_grad": (i, [vp, vp, vp, i, dp, vp]),
+        "iccg_mpnn_train_step": (i, [vp, vp, vp, i, ctypes.c_float, dp]),
+        "iccg_mpnn_predict": (i, [vp, vp, i, vp]),
+        "iccg_mpnn_destroy": (None, [vp]),
         "ic_apply": (i, [vp, vp, vp]),
         "ic_forward": (i, [vp, vp, vp]),
         "ic_backward": (i, [vp, vp, vp]),
@@ -256,6 +267,9 @@ class Context:
             raise IccgError(st, "iccg_set_factor", f"rejected at row {row.value}")
         _check(st, "iccg_set_factor")
 
+    def restore_ic0(self) -> None:
+        _check(load().iccg_restore_ic0(self._h), "iccg_restore_ic0")
+
     def get_factor(self) -> np.ndarray:
         out = np.zeros(self.nnz, dtype=np.float64)
         _check(load().iccg_get_factor(self._h, out.ctypes.data), "iccg_get_factor")
@@ -339,3 +353,79 @@ def iccg_solve(ctx: Context, b, x, tol: float = 1e-8, maxit: int = 10000):
 
 def iccg_destroy(ctx: Context) -> None:
     ctx.close()
+
+
+# ---------------------------------------------------------------------------
+# learned factor form
+# ---------------------------------------------------------------------------
+def mpnn_param_shapes():
+    """Parameter blocks in the library's layout (include/iccg.h)."""
+    shapes = []
+    for d in (3, 32, 32):
+        shapes += [("Ws", (32, d)), ("b", (32,)), ("Wm", (32, d + 4)), ("bm", (32,))]
+    shapes += [("Wr", (32, 68)), ("br", (32,)), ("wo", (32,)), ("bo", (1,))]
+    return shapes
+
+
+class Network:
+    """Owns one iccg_mpnn (FP32 master parameters, Adam state, work buffers)."""
+
+    def __init__(self, params, stream=None):
+        import torch
+        lib = load()
+        self.count = lib.iccg_mpnn_param_count()
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        if p.size != self.count:
+            raise ValueError(f"expected {self.count} parameters, got {p.size}")
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        h = ctypes.c_void_p()
+        _check(lib.iccg_mpnn_create(ctypes.byref(h), p.ctypes.data, ctypes.c_void_p(stream.cuda_stream)),
+               "iccg_mpnn_create")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().iccg_mpnn_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def params(self) -> np.ndarray:
+        out = np.zeros(self.count, dtype=np.float32)
+        _check(load().iccg_mpnn_get_params(self._h, out.ctypes.data), "iccg_mpnn_get_params")
+        return out
+
+    def set_params(self, params) -> None:
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        _check(load().iccg_mpnn_set_params(self._h, p.ctypes.data), "iccg_mpnn_set_params")
+
+    def loss_grad(self, ctx: Context, probes_dev):
+        loss = ctypes.c_double(0.0)
+        grad = np.zeros(self.count, dtype=np.float32)
+        nprobes = probes_dev.shape[0]
+        _check(load().iccg_mpnn_loss_grad(self._h, ctx._h, _ptr(probes_dev), nprobes,
+                                          ctypes.byref(loss), grad.ctypes.data), "iccg_mpnn_loss_grad")
+        return loss.value, grad
+
+    def train_step(self, ctx: Context, probes_dev, lr: float = 1e-3, want_loss: bool = True):
+        loss = ctypes.c_double(0.0)
+        nprobes = probes_dev.shape[0]
+        _check(load().iccg_mpnn_train_step(self._h, ctx._h, _ptr(probes_dev), nprobes, float(lr),
+                                           ctypes.byref(loss) if want_loss else None),
+               "iccg_mpnn_train_step")
+        return loss.value if want_loss else None
+
+    def predict(self, ctx: Context, out_dev, bf16: bool = True) -> None:
+        _check(load().iccg_mpnn_predict(self._h, ctx._h, 1 if bf16 else 0, _ptr(out_dev)),
+               "iccg_mpnn_predict")

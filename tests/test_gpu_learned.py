@@ -1,0 +1,156 @@
+"""GPU tests of the learned-factor form against the FP64 network oracle.
+
+Tolerances: the GPU trains in FP32, so the probe loss matches the FP64 oracle
+to 1e-5 relative and every parameter block's gradient to 1e-3 relative
+(norm-wise); the zero-initialized output layer reproduces IC(0) bit for bit.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from oracle import mpnn
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+from paper_2609_00561_amd import iccg  # noqa: E402
+
+
+def _matrix(m=8, seed=3, sigma=1.0):
+    rng = np.random.default_rng(seed)
+    A = synth.grid3d_7pt_lognormal(m, m, m, sigma, 1e-6, rng)
+    o = iccg.iccg_order_abmc(A, 64)
+    ref = oracle.order_abmc(A, 64)
+    rp, cl, vl = iccg.iccg_permute(A, o.perm)
+    Ap = oracle.permute(A, ref.perm)
+    lval, _ = oracle.ic0(Ap)
+    b = synth.uniform_rhs(A.n, rng)
+    return o, (rp, cl, vl), Ap, lval, b[ref.perm]
+
+
+def _ctx(o, csr, **kw):
+    ctx = iccg.Context(*csr, o.block_ptr, o.color_ptr, **kw)
+    ctx.ic0_factor()
+    return ctx
+
+
+def _theta(seed):
+    th = synth.glorot_params(mpnn.param_shapes(), seed)
+    rng = np.random.default_rng(seed + 1)
+    return th + 0.05 * rng.standard_normal(th.size)
+
+
+def test_layouts_agree():
+    assert iccg.load().iccg_mpnn_param_count() == mpnn.param_count()
+    assert iccg.mpnn_param_shapes() == mpnn.param_shapes()
+
+
+@pytest.mark.parametrize("m,seed", [(6, 1), (8, 2)])
+def test_loss_and_gradient_vs_oracle(m, seed):
+    o, csr, Ap, lval, _ = _matrix(m, seed)
+    th = _theta(seed)
+    th32 = th.astype(np.float32)
+    Z = np.random.default_rng(seed + 7).standard_normal((8, Ap.n))
+    g = mpnn.Graph(Ap)
+    L_ref, G_ref = mpnn.loss_and_grad(th32.astype(np.float64), Ap, lval, g, Z)
+    with _ctx(o, csr) as ctx, iccg.Network(th32) as net:
+        L, G = net.loss_grad(ctx, torch.tensor(Z, device="cuda"))
+    assert L == pytest.approx(L_ref, rel=1e-5)
+    k = 0
+    for name, shp in mpnn.param_shapes():
+        size = int(np.prod(shp))
+        ref, got = G_ref[k:k + size], G[k:k + size].astype(np.float64)
+        err = np.linalg.norm(got - ref) / max(np.linalg.norm(ref), 1e-30)
+        print(name, shp, "grad rel err", err)
+        assert err <= 1e-3, (name, err)
+        k += size
+
+
+def test_zero_output_layer_reproduces_ic0_and_solve():
+    o, csr, Ap, lval, bp = _matrix(8, 4)
+    th = synth.glorot_params(iccg.mpnn_param_shapes(), 5).astype(np.float32)
+    with _ctx(o, csr) as ctx, iccg.Network(th) as net:
+        x0 = torch.zeros(Ap.n, dtype=torch.float64, device="cuda")
+        r0 = ctx.solve(torch.tensor(bp, device="cuda"), x0)
+        lv = torch.zeros(Ap.nnz, dtype=torch.float64, device="cuda")
+        for bf16 in (True, False):
+            net.predict(ctx, lv, bf16=bf16)
+            got = lv.cpu().numpy()
+            assert np.array_equal(got, np.where(mpnn.Graph(Ap).lower, lval, 0.0))
+        ctx.set_factor(lv)
+        x1 = torch.zeros_like(x0)
+        r1 = ctx.solve(torch.tensor(bp, device="cuda"), x1)
+        assert r1["iters"] == r0["iters"]
+        assert torch.equal(x0, x1)
+
+
+def test_bf16_inference_close_to_fp32():
+    o, csr, Ap, lval, _ = _matrix(8, 6)
+    th = _theta(9).astype(np.float32)
+    with _ctx(o, csr) as ctx, iccg.Network(th) as net:
+        a = torch.zeros(Ap.nnz, dtype=torch.float64, device="cuda")
+        b = torch.zeros_like(a)
+        net.predict(ctx, a, bf16=False)
+        net.predict(ctx, b, bf16=True)
+        a, b = a.cpu().numpy(), b.cpu().numpy()
+    lower = mpnn.Graph(Ap).lower
+    corr_a = a[lower] - lval[lower]
+    corr_b = b[lower] - lval[lower]
+    rel = np.linalg.norm(corr_a - corr_b) / np.linalg.norm(corr_a)
+    print("bf16 vs fp32 correction rel diff", rel)
+    assert rel < 0.05
+    # FP32 inference matches the oracle forward
+    g = mpnn.Graph(Ap)
+    lt, cache = mpnn.forward(th.astype(np.float64), Ap, lval, g)
+    ref = mpnn.factor_from_scaled(g, lt, cache["s"])
+    assert np.max(np.abs(a - ref)) <= 1e-5 * np.max(np.abs(ref))
+
+
+def test_training_reduces_probe_loss():
+    mats = [_matrix(8, s) for s in range(3)]
+    th = synth.glorot_params(iccg.mpnn_param_shapes(), 11).astype(np.float32)
+    rng = np.random.default_rng(0)
+    ctxs = [_ctx(o, csr) for o, csr, *_ in mats]
+    with iccg.Network(th) as net:
+        first = []
+        for ctx, (o, csr, Ap, *_r) in zip(ctxs, mats):
+            Z = torch.tensor(rng.standard_normal((8, Ap.n)), device="cuda")
+            first.append(net.loss_grad(ctx, Z)[0])
+        for step in range(60):
+            for ctx, (o, csr, Ap, *_r) in zip(ctxs, mats):
+                Z = torch.tensor(rng.standard_normal((8, Ap.n)), device="cuda")
+                net.train_step(ctx, Z, lr=1e-3, want_loss=False)
+        last = []
+        rng2 = np.random.default_rng(0)
+        for ctx, (o, csr, Ap, *_r) in zip(ctxs, mats):
+            Z = torch.tensor(rng2.standard_normal((8, Ap.n)), device="cuda")
+            last.append(net.loss_grad(ctx, Z)[0])
+    for c in ctxs:
+        c.close()
+    print("probe loss before", first, "after", last)
+    assert np.mean(last) < np.mean(first)
+
+
+def test_negative_pivot_falls_back():
+    """An injected non-positive pivot in the predicted factor is rejected by
+    iccg_set_factor and the IC(0) factor stays in place."""
+    o, csr, Ap, lval, bp = _matrix(8, 8)
+    th = synth.glorot_params(iccg.mpnn_param_shapes(), 12).astype(np.float32)
+    th[-1] = -1e4     # b_o: drives every predicted entry far negative
+    with _ctx(o, csr) as ctx, iccg.Network(th) as net:
+        lv = torch.zeros(Ap.nnz, dtype=torch.float64, device="cuda")
+        net.predict(ctx, lv, bf16=True)
+        with pytest.raises(iccg.IccgError) as e:
+            ctx.set_factor(lv)
+        assert e.value.status == iccg.ICCG_EBREAKDOWN
+        got = ctx.get_factor()
+    assert np.array_equal(got, np.where(mpnn.Graph(Ap).lower, lval, 0.0))
