@@ -47,6 +47,9 @@ def parse():
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=40)
+    ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--learned-matrices", type=int, default=256)
+    ap.add_argument("--learned-epochs", type=int, default=3)
     ap.add_argument("--seed", type=int, default=42)
     return ap.parse_args()
 
@@ -198,6 +201,37 @@ def main():
                        "speedup_vs_fp64": round(ms_per_step / (1e3 * float(np.median(times32))), 3)}
         ctx32.close()
         log(f"[bench] FP32 form: {out['fp32']}")
+
+    if not args.no_learned:
+        from paper_2609_00561_amd import learned
+        import synth as _synth
+        tl0 = time.time()
+        ctxs = []
+        for k in range(args.learned_matrices):
+            Ak, _ = _synth.workload("lognormal7_32", k)
+            ctxs.append(learned.build_context(Ak, 64)[0])
+        t_setup = time.time() - tl0
+        with iccg.Network(learned.init_params(0)) as net:
+            tt = time.time()
+            hist = learned.train(net, ctxs, args.learned_epochs, lr=1e-3, seed=0, log=log)
+            torch.cuda.synchronize()
+            t_train = time.time() - tt
+            for c_ in ctxs:
+                c_.close()
+            ev = learned.solve_both(net, ctx, torch.tensor(bp, device=dev), tol=args.tol)
+        out["learned"] = {
+            "train": {"matrices": args.learned_matrices, "grid": "32^3", "epochs": args.learned_epochs,
+                      "probe_loss_by_epoch": [round(v, 5) for v in hist],
+                      "train_s": round(t_train, 2), "setup_s": round(t_setup, 2)},
+            "plain_iters": ev["plain_iters"], "plain_ms": round(ev["plain_ms"], 3),
+            "learned_iters": ev.get("learned_iters"),
+            "learned_ms": round(ev["learned_ms"], 3) if "learned_ms" in ev else None,
+            "inference_ms": round(ev["infer_ms"], 3), "pivot_ok": ev["pivot_ok"], "kept": ev["kept"],
+            "x_rel_diff_vs_plain": ev.get("x_rel_diff"),
+            "speedup_vs_fp64_incl_inference": (round(ev["plain_ms"] / (ev["learned_ms"] + ev["infer_ms"]), 3)
+                                               if "learned_ms" in ev else None),
+        }
+        log(f"[bench] learned form: {out['learned']}")
 
     if not args.no_cpu:
         import oracle

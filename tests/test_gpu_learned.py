@@ -154,3 +154,31 @@ def test_negative_pivot_falls_back():
         assert e.value.status == iccg.ICCG_EBREAKDOWN
         got = ctx.get_factor()
     assert np.array_equal(got, np.where(mpnn.Graph(Ap).lower, lval, 0.0))
+
+
+def test_trained_network_on_unseen_matrices():
+    """Train on seeded 32^3 lognormal matrices, then compare learned and plain
+    IC(0) on unseen seeds.  The printed gains are reported, not pinned (no
+    paper number exists); the fallback rule is pinned: the factor kept never
+    needs more iterations than plain IC(0)."""
+    from paper_2609_00561_amd import learned
+    train_ctxs = [learned.build_context(synth.workload("lognormal7_32", k)[0], 64)[0]
+                  for k in range(16)]
+    with iccg.Network(learned.init_params(0)) as net:
+        hist = learned.train(net, train_ctxs, epochs=6, lr=1e-3, seed=1)
+        for c in train_ctxs:
+            c.close()
+        print("probe loss by epoch", hist)
+        assert hist[-1] < hist[0]
+        for seed in (10000, 10001, 10002):
+            A, b = synth.workload("lognormal7_32", seed)
+            ctx, order = learned.build_context(A, 64)
+            with ctx:
+                ev = learned.solve_both(net, ctx, torch.tensor(b[order.perm], device="cuda"))
+                print("unseen seed", seed, ev)
+                kept_iters = ev["learned_iters"] if ev["kept"] == "learned" else ev["plain_iters"]
+                assert kept_iters <= ev["plain_iters"]
+                # after the choice the context holds the kept factor
+                x = torch.zeros(ctx.n, dtype=torch.float64, device="cuda")
+                r = ctx.solve(torch.tensor(b[order.perm], device="cuda"), x)
+                assert r["iters"] == kept_iters
