@@ -67,9 +67,12 @@ typedef struct {
     int   pack_rows;    /* max rows one wavefront task packs from consecutive small
                            blocks of one color (1..64, default 64)                */
     int   use_graph;    /* 1 = replay the iteration batch as a captured HIP graph  */
+    int   sweep_launch; /* 0 = one kernel launch per color (default); 1 = one launch
+                           per sweep, each wavefront task waiting only for the
+                           earlier-color tasks it reads (same arithmetic)         */
 } iccg_options;
 
-/* Fills *opt with the defaults above (FP64, null stream, 32, 64, 1). */
+/* Fills *opt with the defaults above (FP64, null stream, 32, 64, 1, 0). */
 void iccg_default_options(iccg_options *opt);
 
 /* ------------------------------------------------------------------------ */

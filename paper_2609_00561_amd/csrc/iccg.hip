@@ -161,33 +161,29 @@ __global__ void k_init_scalars(DevScalars *sc, double tol, int maxit, int hist_c
 // SpMV on the sliced ELL copy (one wavefront per 64-row slice, one lane per row)
 //   SP_PLAIN: y = A x, partial (x, y)
 //   SP_RESID: y = b - A x, partial (y, y)
-//   SP_CG:    p_new = z + beta p_old (formed on the fly for every gathered
-//             entry and stored for the own row), y = A p_new, partial (p_new, y);
-//             x is p_old here.
 // ---------------------------------------------------------------------------
-enum SpmvMode : int { SP_PLAIN = 0, SP_RESID = 1, SP_CG = 2 };
+enum SpmvMode : int { SP_PLAIN = 0, SP_RESID = 1 };
 
 // One wavefront workgroup per slice (grid-stride over slices); WMAX slots of a
 // row are loaded into registers at once, then all gathers, then the row sum in
 // ascending column order.
 template <int MODE, int WMAX>
-__global__ __launch_bounds__(64) void k_spmv(int n, int nslices, const int *__restrict__ slice_off,
+__global__ __launch_bounds__(64) void k_spmv(int n, int nslices, const int *__restrict__ slice_order,
+                                             const int *__restrict__ slice_off,
                                              const int *__restrict__ slice_w,
                                              const int *__restrict__ col,
                                              const double *__restrict__ val,
                                              const double *__restrict__ x,
                                              double *__restrict__ y,
                                              const double *__restrict__ b,
-                                             const double *__restrict__ z,
-                                             double *__restrict__ pnew,
                                              double *__restrict__ part,
                                              const DevScalars *sc) {
     if (sc && sc->done != DONE_RUNNING) return;
     const int lane = threadIdx.x;
     const int wg = xcd_remap(blockIdx.x, gridDim.x);
-    const double beta = (MODE == SP_CG) ? sc->beta : 0.0;
     double acc = 0.0;
-    for (int sl = wg; sl < nslices; sl += gridDim.x) {
+    for (int lg = wg; lg < nslices; lg += gridDim.x) {
+        const int sl = slice_order[lg];
         const int off = slice_off[sl] + lane, w = slice_w[sl];
         const int row = sl * 64 + lane;
         int cc[WMAX];
@@ -198,47 +194,30 @@ __global__ __launch_bounds__(64) void k_spmv(int n, int nslices, const int *__re
                 cc[k] = col[off + k * 64];
                 vv[k] = val[off + k * 64];
             }
-        double own_z = 0.0, own_x = 0.0, own_b = 0.0;
+        double own_x = 0.0, own_b = 0.0;
         if (row < n) {
             own_x = x[row];
-            if (MODE == SP_CG) own_z = z[row];
             if (MODE == SP_RESID) own_b = b[row];
         }
-        double zv[WMAX];
 #pragma unroll
         for (int k = 0; k < WMAX; ++k)
-            if (k < w) {
-                const int c = cc[k] < 0 ? 0 : cc[k];
-                xv[k] = x[c];
-                if (MODE == SP_CG) zv[k] = z[c];
-            }
+            if (k < w) xv[k] = x[cc[k] < 0 ? 0 : cc[k]];
         double sum = 0.0;
 #pragma unroll
         for (int k = 0; k < WMAX; ++k)
-            if (k < w) {
-                const double v = (MODE == SP_CG) ? zv[k] + beta * xv[k] : xv[k];
-                sum = (cc[k] >= 0) ? sum + vv[k] * v : sum;
-            }
+            if (k < w) sum = (cc[k] >= 0) ? sum + vv[k] * xv[k] : sum;
         for (int k = WMAX; k < w; ++k) {
             const int c = col[off + k * 64];
-            if (c >= 0) {
-                const double v = (MODE == SP_CG) ? z[c] + beta * x[c] : x[c];
-                sum += val[off + k * 64] * v;
-            }
+            if (c >= 0) sum += val[off + k * 64] * x[c];
         }
         if (row < n) {
             if (MODE == SP_PLAIN) {
                 y[row] = sum;
                 acc += own_x * sum;
-            } else if (MODE == SP_RESID) {
+            } else {
                 const double rv = own_b - sum;
                 y[row] = rv;
                 acc += rv * rv;
-            } else {
-                const double pn = own_z + beta * own_x;
-                pnew[row] = pn;
-                y[row] = sum;
-                acc += pn * sum;
             }
         }
     }
@@ -263,6 +242,17 @@ __global__ __launch_bounds__(kVecThreads) void k_dot(int n, const double *__rest
 __global__ __launch_bounds__(kVecThreads) void k_fill(int n, double *__restrict__ dst, double v) {
     for (int i = blockIdx.x * kVecThreads + threadIdx.x; i < n; i += gridDim.x * kVecThreads)
         dst[i] = v;
+}
+
+// p = z + beta p
+__global__ __launch_bounds__(kVecThreads) void k_update_p(int n, double *__restrict__ p,
+                                                          const double *__restrict__ z,
+                                                          const DevScalars *sc) {
+    if (sc->done != DONE_RUNNING) return;
+    const double beta = sc->beta;
+    const int wg = xcd_remap(blockIdx.x, gridDim.x);
+    for (int i = wg * kVecThreads + threadIdx.x; i < n; i += gridDim.x * kVecThreads)
+        p[i] = z[i] + beta * p[i];
 }
 
 template <typename A, typename B>
@@ -350,13 +340,32 @@ struct CgArgs {
 };
 
 // One chunk of a task: see k_sweep.
-template <typename F, bool FWD, int KMAX, int MODE, typename TIn, typename TOut>
+struct NoWait {
+    __device__ void operator()() const {}
+};
+
+// Device-scope (agent) relaxed accesses: they bypass the non-coherent caches,
+// so values written by one XCD are read correctly by another once the writer
+// has waited for its stores and raised a flag.  Used for the values that cross
+// tasks inside one single-launch sweep.
+template <typename T>
+__device__ __forceinline__ T load_coherent(const T *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ void store_coherent(T *p, T v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <typename F, bool FWD, int KMAX, int MODE, typename TIn, typename TOut, class Wait = NoWait,
+          bool COH = false>
 __device__ __forceinline__ void sweep_chunk(const Chunk &ch, const uint32_t *__restrict__ meta,
                                             const int *__restrict__ scol,
                                             const F *__restrict__ sval,
                                             const F *__restrict__ inv,
                                             const TIn *__restrict__ in, TOut *__restrict__ out,
-                                            const CgArgs &cg, double alpha, F *ys, double &dacc) {
+                                            const CgArgs &cg, double alpha, F *ys, double &dacc,
+                                            const Wait &wait = Wait()) {
     const int t = threadIdx.x;
     const int nr = ch.shape & 0xffff, W = ch.shape >> 16;
     const bool active = t < nr;
@@ -389,6 +398,8 @@ __device__ __forceinline__ void sweep_chunk(const Chunk &ch, const uint32_t *__r
         }
         if (MODE == SW_DOT_BWD) rd = cg.rdot[i];
     }
+    // values of other tasks are read only after their producers published them
+    wait();
     const int ne = m & 0xffffu, ni = (m >> 16) & 0xffu, lev = m >> 24;
     if (active) {
         // all gathers at once (the chunk width is uniform); slots that are not
@@ -396,13 +407,17 @@ __device__ __forceinline__ void sweep_chunk(const Chunk &ch, const uint32_t *__r
         F g[KMAX];
 #pragma unroll
         for (int k = 0; k < KMAX; ++k)
-            if (k < W) g[k] = static_cast<F>(out[cc[k] < 0 ? 0 : cc[k]]);
+            if (k < W) {
+                const TOut *src = out + (cc[k] < 0 ? 0 : cc[k]);
+                g[k] = static_cast<F>(COH ? load_coherent(src) : *src);
+            }
 #pragma unroll
         for (int k = 0; k < KMAX; ++k)
             if (k < W) s = (k < ne) ? s - vv[k] * g[k] : s;
         for (int k = KMAX; k < ne; ++k) {
             const int sl = base + k * nr;
-            s -= sval[sl] * static_cast<F>(out[scol[sl]]);
+            const TOut *src = out + scol[sl];
+            s -= sval[sl] * static_cast<F>(COH ? load_coherent(src) : *src);
         }
     }
     for (int L = 0; L < ch.depth; ++L) {
@@ -420,7 +435,8 @@ __device__ __forceinline__ void sweep_chunk(const Chunk &ch, const uint32_t *__r
     }
     if (active) {
         const F yv = ys[t];
-        out[i] = static_cast<TOut>(yv);
+        if (COH) store_coherent(out + i, static_cast<TOut>(yv));
+        else out[i] = static_cast<TOut>(yv);
         if (MODE == SW_DOT_BWD) dacc += rd * static_cast<double>(yv);
     }
 }
@@ -462,6 +478,98 @@ __global__ __launch_bounds__(64) void k_sweep(const TaskRec *__restrict__ tasks,
     }
 }
 
+// Single-launch sweep: every task of every color in one grid.  Workgroup b
+// runs task wg_task[b]; the table lists the tasks in processing order
+// (forward: colors ascending, backward: descending), so every task a
+// workgroup waits for belongs to a workgroup with a smaller index, which the
+// in-order dispatch has already started; that guarantees progress.  A task
+// waits for the tasks it reads (its dependency list) by polling their flags,
+// which hold the number (epoch) of the sweep that last completed them; a
+// finished task publishes its results with an agent-scope release store of
+// the current epoch.  The epoch is bumped by a one-thread kernel before every
+// launch, so flags are never reset.  A wait that exceeds the spin limit sets
+// *err and continues, so every wavefront always exits.
+struct SyncArgs {
+    const int *epoch;
+    int *flags;
+    const int *dep_ptr;
+    const int *deps;
+    const int *wg_task;
+    int spin_limit;
+    int *err;
+};
+
+__global__ void k_bump_epoch(int *epoch, const DevScalars *sc) {
+    if (threadIdx.x == 0 && blockIdx.x == 0 && !(sc && sc->done != DONE_RUNNING)) *epoch += 1;
+}
+
+struct DepWait {
+    const SyncArgs *sy;
+    int task, epoch;
+    __device__ void operator()() const {
+        // one lane per dependency polls its flag
+        const int d0 = sy->dep_ptr[task], d1 = sy->dep_ptr[task + 1];
+        for (int d = d0 + static_cast<int>(threadIdx.x); d < d1; d += 64) {
+            const int *f = sy->flags + sy->deps[d];
+            int spins = 0;
+            while (__hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < epoch) {
+                __builtin_amdgcn_s_sleep(1);
+                ++spins;
+                // after any timeout every other wait gives up at once
+                if ((spins & 255) == 0 &&
+                    __hip_atomic_load(sy->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+                    break;
+                if (spins > sy->spin_limit) {
+                    __hip_atomic_store(sy->err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    break;
+                }
+            }
+        }
+        // the gathers that follow are device-scope loads issued after the
+        // flags were seen, so they read the producers' device-scope stores
+        __syncthreads();
+    }
+};
+
+template <typename F, bool FWD, int KMAX, int MODE, typename TIn, typename TOut>
+__global__ __launch_bounds__(64) void k_sweep_dep(const TaskRec *__restrict__ tasks,
+                                                  const Chunk *__restrict__ chunks,
+                                                  const uint32_t *__restrict__ meta,
+                                                  const int *__restrict__ scol,
+                                                  const F *__restrict__ sval,
+                                                  const F *__restrict__ inv, SyncArgs sy,
+                                                  const TIn *__restrict__ in,
+                                                  TOut *__restrict__ out, CgArgs cg) {
+    if (cg.sc && cg.sc->done != DONE_RUNNING) return;
+    __shared__ F ys[kChunkRows];
+    const int epoch = *sy.epoch;
+    const int task = sy.wg_task[blockIdx.x];
+    const TaskRec tr = tasks[task];
+    const double alpha = (MODE == SW_CG_FWD) ? cg.sc->alpha : 0.0;
+    double dacc = 0.0;
+    const DepWait wait{&sy, task, epoch};
+    sweep_chunk<F, FWD, KMAX, MODE, TIn, TOut, DepWait, true>(tr.first, meta, scol, sval, inv, in,
+                                                             out, cg, alpha, ys, dacc, wait);
+    for (int q = 1; q < tr.nchunks; ++q) {
+        __builtin_amdgcn_s_waitcnt(0);   // this chunk's stores are complete before they are read
+        __syncthreads();
+        const Chunk ch = chunks[FWD ? tr.c0 + q : tr.c1 - 1 - q];
+        sweep_chunk<F, FWD, KMAX, MODE, TIn, TOut, NoWait, true>(ch, meta, scol, sval, inv, in, out,
+                                                                 cg, alpha, ys, dacc);
+    }
+    if (MODE != SW_APPLY) {
+        const double tsum = wave_sum(dacc);
+        if (threadIdx.x == 0) cg.part[task] = tsum;
+    }
+    // publish: this wavefront's device-scope stores are complete before the
+    // flag is raised
+    __builtin_amdgcn_s_waitcnt(0);
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __syncthreads();
+    if (threadIdx.x == 0)
+        __hip_atomic_store(sy.flags + task, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 namespace {
 
 int grid_for(long long items, int threads, int cap) {
@@ -472,20 +580,20 @@ int grid_for(long long items, int threads, int cap) {
 }
 
 int launch_spmv(iccg_ctx *c, int mode, const double *x, double *y, const double *b,
-                const double *z, double *pnew, const DevScalars *sc) {
+                const DevScalars *sc) {
     dim3 grid(c->spmv_blocks), block(64);
     if (c->prof) c->prof->begin(c->work);
-#define SPMV_ARGS c->n, c->nslices, c->sell_off.p, c->sell_w.p, c->sell_col.p, c->sell_val.p, x, y, b, z, pnew, c->part.p, sc
+#define SPMV_ARGS c->n, c->nslices, c->sell_order.p, c->sell_off.p, c->sell_w.p, c->sell_col.p, c->sell_val.p, x, y, b, c->part.p, sc
 #define SPMV_W(M)                                                                              \
     switch (c->sell_wmax) {                                                                    \
         case 8: hipLaunchKernelGGL((k_spmv<M, 8>), grid, block, 0, c->work, SPMV_ARGS); break;   \
         case 16: hipLaunchKernelGGL((k_spmv<M, 16>), grid, block, 0, c->work, SPMV_ARGS); break; \
         default: hipLaunchKernelGGL((k_spmv<M, 32>), grid, block, 0, c->work, SPMV_ARGS); break; \
     }
-    switch (mode) {
-        case SP_PLAIN: SPMV_W(SP_PLAIN) break;
-        case SP_RESID: SPMV_W(SP_RESID) break;
-        default: SPMV_W(SP_CG) break;
+    if (mode == SP_PLAIN) {
+        SPMV_W(SP_PLAIN)
+    } else {
+        SPMV_W(SP_RESID)
     }
 #undef SPMV_W
 #undef SPMV_ARGS
@@ -511,17 +619,42 @@ SweepArgs<F> sweep_args(const iccg_ctx *c, const DevSweep &s) {
     return a;
 }
 
-// All colors of one sweep direction, one launch per color (colors ascending
-// for the forward sweep, descending for the backward sweep).
+// All colors of one sweep direction: one launch per color (colors ascending
+// for the forward sweep, descending for the backward sweep), or one launch for
+// all of them with per-task dependency waits.
 template <typename F, bool FWD, int MODE>
 int launch_sweep_t(iccg_ctx *c, const void *in, void *out, const CgArgs &cg) {
     using TIn = typename std::conditional<FWD, double, F>::type;
     using TOut = typename std::conditional<FWD, F, double>::type;
-    const DevSweep &d = FWD ? c->fwd : c->bwd;
+    DevSweep &d = FWD ? c->fwd : c->bwd;
     const SweepArgs<F> a = sweep_args<F>(c, d);
-#define SWEEP_ARGS a.tasks, a.chunks, a.meta, a.scol, a.sval, a.inv, t0, t1 - t0, pin, pout, cg
     const TIn *pin = static_cast<const TIn *>(in);
     TOut *pout = static_cast<TOut *>(out);
+    if (c->opt.sweep_launch == 1) {
+        SyncArgs sy;
+        sy.epoch = d.epoch.p;
+        sy.flags = d.flags.p;
+        sy.dep_ptr = d.dep_ptr.p;
+        sy.deps = d.deps.p;
+        sy.wg_task = d.wg_task.p;
+        sy.spin_limit = 1 << 18;
+        sy.err = c->sweep_err.p;
+        hipLaunchKernelGGL(k_bump_epoch, dim3(1), dim3(64), 0, c->work, d.epoch.p, cg.sc);
+        if (c->prof) c->prof->begin(c->work);
+        const dim3 grid(d.ntasks), block(64);
+#define DEP_ARGS a.tasks, a.chunks, a.meta, a.scol, a.sval, a.inv, sy, pin, pout, cg
+        switch (d.kmax) {
+            case 4: hipLaunchKernelGGL((k_sweep_dep<F, FWD, 4, MODE, TIn, TOut>), grid, block, 0, c->work, DEP_ARGS); break;
+            case 8: hipLaunchKernelGGL((k_sweep_dep<F, FWD, 8, MODE, TIn, TOut>), grid, block, 0, c->work, DEP_ARGS); break;
+            case 16: hipLaunchKernelGGL((k_sweep_dep<F, FWD, 16, MODE, TIn, TOut>), grid, block, 0, c->work, DEP_ARGS); break;
+            default: hipLaunchKernelGGL((k_sweep_dep<F, FWD, 32, MODE, TIn, TOut>), grid, block, 0, c->work, DEP_ARGS); break;
+        }
+#undef DEP_ARGS
+        if (c->prof) c->prof->end(c->work, FWD ? PK_FWD : PK_BWD);
+        HIP_CHECK(hipGetLastError());
+        return ICCG_OK;
+    }
+#define SWEEP_ARGS a.tasks, a.chunks, a.meta, a.scol, a.sval, a.inv, t0, t1 - t0, pin, pout, cg
     for (int step = 0; step < c->ncolors; ++step) {
         const int col = FWD ? step : c->ncolors - 1 - step;
         const int t0 = d.color_task_ptr[col], t1 = d.color_task_ptr[col + 1];
@@ -538,6 +671,16 @@ int launch_sweep_t(iccg_ctx *c, const void *in, void *out, const CgArgs &cg) {
     }
 #undef SWEEP_ARGS
     HIP_CHECK(hipGetLastError());
+    return ICCG_OK;
+}
+
+// fails loudly if a dependency wait of the single-launch sweep timed out
+int check_sweep_err(iccg_ctx *c) {
+    if (c->opt.sweep_launch != 1) return ICCG_OK;
+    int err = 0;
+    HIP_CHECK(hipMemcpyAsync(&err, c->sweep_err.p, sizeof(int), hipMemcpyDeviceToHost, c->work));
+    HIP_CHECK(hipStreamSynchronize(c->work));
+    if (err) return set_error(ICCG_EHIP, "a sweep dependency wait exceeded its spin limit");
     return ICCG_OK;
 }
 
@@ -562,21 +705,23 @@ int launch_reduce(iccg_ctx *c, int np, int op, double *out) {
     return ICCG_OK;
 }
 
-// CG iteration j (1-based; all kernels return at once after the stopping
-// test passed).  The search direction alternates between the two p buffers:
-// iteration j reads p_{j-1} from pbuf[(j+1)%2] and writes p_j to pbuf[j%2].
-//   1. SpMV:     p_j = z + beta p_{j-1}, q = A p_j, alpha = rho / (p_j, q)
-//   2. forward:  x += alpha p_j, r -= alpha q, ||r|| stopping test, y = L^{-1} r
-//   3. backward: z = L^{-T} y, beta = (r, z)/rho, rho = (r, z)
+// One CG iteration (all kernels return at once after the stopping test passed):
+//   1. p = z + beta p (beta = 0 and p = 0 before the first iteration)
+//   2. SpMV:     q = A p, alpha = rho / (p, q)
+//   3. forward:  x += alpha p, r -= alpha q, ||r|| stopping test, y = L^{-1} r
+//   4. backward: z = L^{-T} y, beta = (r, z)/rho, rho = (r, z)
 int enqueue_iteration(iccg_ctx *c, long long j) {
+    (void)j;
     DevScalars *sc = c->scal.p;
-    double *p_old = c->pbuf[(j + 1) & 1].p, *p_new = c->pbuf[j & 1].p;
-    ICCG_CHECK(launch_spmv(c, SP_CG, p_old, c->q.p, nullptr, c->z.p, p_new, sc));
+    double *p = c->p.p;
+    hipLaunchKernelGGL(k_update_p, dim3(c->vec_blocks), dim3(kVecThreads), 0, c->work, c->n, p, c->z.p, sc);
+    HIP_CHECK(hipGetLastError());
+    ICCG_CHECK(launch_spmv(c, SP_PLAIN, p, c->q.p, nullptr, sc));
     ICCG_CHECK(launch_reduce(c, c->spmv_blocks, OP_ALPHA, nullptr));
     CgArgs f = no_cg();
     f.x = c->x.p;
     f.r = c->r.p;
-    f.p = p_new;
+    f.p = p;
     f.q = c->q.p;
     f.part = c->part.p;
     f.sc = sc;
@@ -591,8 +736,7 @@ int enqueue_iteration(iccg_ctx *c, long long j) {
     return ICCG_OK;
 }
 
-// Batches start at odd iteration numbers and hold an even number of
-// iterations, so one captured graph serves every batch.
+// A batch of iterations; one captured graph serves every batch.
 int enqueue_batch(iccg_ctx *c, long long j0, int iters) {
     for (int k = 0; k < iters; ++k) ICCG_CHECK(enqueue_iteration(c, j0 + k));
     return ICCG_OK;
@@ -659,6 +803,14 @@ int upload_sweep(iccg_ctx *c, const SweepPlan &plan, DevSweep &d) {
     d.kmax = plan.max_width <= 4 ? 4 : plan.max_width <= 8 ? 8 : plan.max_width <= 16 ? 16 : 32;
     d.color_task_ptr = plan.color_task_ptr;
     ICCG_CHECK(d.tasks.upload(plan.tasks.data(), plan.tasks.size(), c->work));
+    ICCG_CHECK(d.dep_ptr.upload(plan.dep_ptr.data(), plan.dep_ptr.size(), c->work));
+    d.ndeps = static_cast<long long>(plan.deps.size());
+    ICCG_CHECK(d.deps.upload(plan.deps.data(), plan.deps.size(), c->work));
+    ICCG_CHECK(d.wg_task.upload(plan.wg_task.data(), plan.wg_task.size(), c->work));
+    ICCG_CHECK(d.flags.alloc(std::max(d.ntasks, 1)));
+    ICCG_CHECK(d.epoch.alloc(1));
+    HIP_CHECK(hipMemsetAsync(d.flags.p, 0, sizeof(int) * std::max(d.ntasks, 1), c->work));
+    HIP_CHECK(hipMemsetAsync(d.epoch.p, 0, sizeof(int), c->work));
     ICCG_CHECK(d.chunks.upload(plan.chunks.data(), plan.chunks.size(), c->work));
     ICCG_CHECK(d.meta.upload(plan.meta.data(), plan.meta.size(), c->work));
     ICCG_CHECK(d.scol.upload(plan.slot_col.data(), plan.slot_col.size(), c->work));
@@ -731,7 +883,7 @@ int validate(int n, const int *rowptr, const int *col, const double *val, int nb
                                 color_ptr, pack_rows, hs.fwd));
     ICCG_CHECK(build_sweep_plan(false, n, rowptr, col, tpos.data(), nblocks, block_ptr, ncolors,
                                 color_ptr, pack_rows, hs.bwd));
-    ICCG_CHECK(build_sell(n, rowptr, col, val, hs.sell));
+    ICCG_CHECK(build_sell(n, rowptr, col, val, block_ptr, ncolors, color_ptr, hs.sell));
     return ICCG_OK;
 }
 
@@ -765,11 +917,12 @@ int upload_setup(iccg_ctx *c, int n, const int *rowptr, const int *col, const do
         ICCG_CHECK(c->inv64.alloc(n));
     }
     ICCG_CHECK(c->y64.alloc(n));
-    for (DevArray<double> *v : {&c->x, &c->r, &c->z, &c->q, &c->b, &c->pbuf[0], &c->pbuf[1]})
+    for (DevArray<double> *v : {&c->x, &c->r, &c->z, &c->q, &c->b, &c->p})
         ICCG_CHECK(v->alloc(n));
 
     c->nslices = static_cast<int>(hs.sell.slice_off.size());
     ICCG_CHECK(c->sell_off.upload(hs.sell.slice_off.data(), hs.sell.slice_off.size(), s));
+    ICCG_CHECK(c->sell_order.upload(hs.sell.order.data(), hs.sell.order.size(), s));
     ICCG_CHECK(c->sell_w.upload(hs.sell.slice_width.data(), hs.sell.slice_width.size(), s));
     ICCG_CHECK(c->sell_col.upload(hs.sell.col.data(), hs.sell.col.size(), s));
     ICCG_CHECK(c->sell_val.upload(hs.sell.val.data(), hs.sell.val.size(), s));
@@ -778,12 +931,14 @@ int upload_setup(iccg_ctx *c, int n, const int *rowptr, const int *col, const do
     int wmax = 0;
     for (int w : hs.sell.slice_width) wmax = std::max(wmax, w);
     c->sell_wmax = wmax <= 8 ? 8 : wmax <= 16 ? 16 : 32;
-    c->spmv_blocks = round8(grid_for(c->nslices, 1, 8192));
+    c->spmv_blocks = c->nslices;   // one wavefront per slice, in launch order
     c->vec_blocks = round8(grid_for(n, kVecThreads, kMaxVecBlocks));
     const int np = std::max({c->spmv_blocks, c->vec_blocks, c->bwd.ntasks, c->fwd.ntasks, 1});
     ICCG_CHECK(c->part.alloc(np));
     ICCG_CHECK(c->scal.alloc(1));
     ICCG_CHECK(c->dint.alloc(1));
+    ICCG_CHECK(c->sweep_err.alloc(1));
+    HIP_CHECK(hipMemsetAsync(c->sweep_err.p, 0, sizeof(int), s));
     ICCG_CHECK(c->hist.alloc(1));
     HIP_CHECK(hipStreamSynchronize(s));
     return ICCG_OK;
@@ -796,7 +951,9 @@ int check_ctx(iccg_ctx *c) {
 
 int read_scalars(iccg_ctx *c) {
     HIP_CHECK(hipMemcpyAsync(c->h_scal, c->scal.p, sizeof(DevScalars), hipMemcpyDeviceToHost, c->work));
+    HIP_CHECK(hipMemcpyAsync(&c->h_err, c->sweep_err.p, sizeof(int), hipMemcpyDeviceToHost, c->work));
     HIP_CHECK(hipStreamSynchronize(c->work));
+    if (c->h_err) return set_error(ICCG_EHIP, "a sweep dependency wait exceeded its spin limit");
     return ICCG_OK;
 }
 
@@ -829,9 +986,9 @@ int solve_impl(iccg_ctx *c, const double *b, double *x, double tol, int maxit, i
     HIP_CHECK(hipGetLastError());
     ICCG_CHECK(enqueue_dot(c, c->b.p, c->b.p, OP_BNORM, nullptr));
     // r = b - A x, stopping test on the initial residual
-    ICCG_CHECK(launch_spmv(c, SP_RESID, c->x.p, c->r.p, c->b.p, nullptr, nullptr, nullptr));
+    ICCG_CHECK(launch_spmv(c, SP_RESID, c->x.p, c->r.p, c->b.p, nullptr));
     ICCG_CHECK(launch_reduce(c, c->spmv_blocks, OP_INIT_RR, nullptr));
-    // z = M^{-1} r, rho = (r, z); p_0 = 0 and beta = 0 make the first SpMV form p_1 = z
+    // z = M^{-1} r, rho = (r, z); p = 0 and beta = 0 make the first update p = z
     CgArgs init = no_cg();
     init.sc = c->scal.p;
     ICCG_CHECK((launch_sweep<true, SW_APPLY>(c, c->r.p, ytmp(c), init)));
@@ -839,10 +996,10 @@ int solve_impl(iccg_ctx *c, const double *b, double *x, double tol, int maxit, i
     init.part = c->part.p;
     ICCG_CHECK((launch_sweep<false, SW_DOT_BWD>(c, ytmp(c), c->z.p, init)));
     ICCG_CHECK(launch_reduce(c, c->bwd.ntasks, OP_RHO, nullptr));
-    hipLaunchKernelGGL(k_fill, dim3(c->vec_blocks), dim3(kVecThreads), 0, s, n, c->pbuf[0].p, 0.0);
+    hipLaunchKernelGGL(k_fill, dim3(c->vec_blocks), dim3(kVecThreads), 0, s, n, c->p.p, 0.0);
     HIP_CHECK(hipGetLastError());
     ICCG_CHECK(read_scalars(c));
-    const int batch = std::max(2, (c->opt.check_every + 1) / 2 * 2);
+    const int batch = std::max(1, c->opt.check_every);
     long long j = 1;
     while (c->h_scal->done == DONE_RUNNING) {
         if (c->prof) {
@@ -858,11 +1015,12 @@ int solve_impl(iccg_ctx *c, const double *b, double *x, double tol, int maxit, i
         }
     }
     // true residual
-    ICCG_CHECK(launch_spmv(c, SP_RESID, c->x.p, c->q.p, c->b.p, nullptr, nullptr, nullptr));
+    ICCG_CHECK(launch_spmv(c, SP_RESID, c->x.p, c->q.p, c->b.p, nullptr));
     ICCG_CHECK(launch_reduce(c, c->spmv_blocks, OP_TRUE, nullptr));
     HIP_CHECK(hipMemcpyAsync(x, c->x.p, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
     HIP_CHECK(hipEventRecord(c->ev_t1, s));
     ICCG_CHECK(read_scalars(c));
+    ICCG_CHECK(check_sweep_err(c));
     float ms = 0.0f;
     HIP_CHECK(hipEventElapsedTime(&ms, c->ev_t0, c->ev_t1));
     c->last_ms = ms;
@@ -904,6 +1062,7 @@ void iccg_default_options(iccg_options *opt) {
     opt->check_every = 32;
     opt->pack_rows = 64;
     opt->use_graph = 1;
+    opt->sweep_launch = 0;
 }
 
 const char *iccg_strerror(int st) {
@@ -937,6 +1096,8 @@ int iccg_setup(iccg_ctx **out, int n, const int *rowptr, const int *col, const d
             return set_error(ICCG_EINVAL, "precision must be ICCG_FP64 or ICCG_FP32");
         if (c->opt.check_every < 1) c->opt.check_every = 1;
         if (c->opt.pack_rows < 1 || c->opt.pack_rows > kChunkRows) c->opt.pack_rows = kChunkRows;
+        if (c->opt.sweep_launch != 0 && c->opt.sweep_launch != 1)
+            return set_error(ICCG_EINVAL, "sweep_launch must be 0 or 1");
         HostSetup hs;
         ICCG_CHECK(validate(n, rowptr, col, val, nblocks, block_ptr, ncolors, color_ptr,
                             c->opt.pack_rows, hs));
@@ -1031,7 +1192,8 @@ int ic_apply(iccg_ctx *c, const double *r, double *z) {
         if (r == z) return set_error(ICCG_EINVAL, "r and z must not alias");
         if (!c->has_factor) return set_error(ICCG_ESTATE, "no factor");
         ICCG_CHECK((launch_sweep<true, SW_APPLY>(c, r, ytmp(c), no_cg())));
-        return launch_sweep<false, SW_APPLY>(c, ytmp(c), z, no_cg());
+        ICCG_CHECK((launch_sweep<false, SW_APPLY>(c, ytmp(c), z, no_cg())));
+        return check_sweep_err(c);
     });
 }
 
@@ -1044,10 +1206,11 @@ int ic_forward(iccg_ctx *c, const double *r, double *y) {
             hipLaunchKernelGGL((k_convert<double, float>), dim3(c->vec_blocks), dim3(kVecThreads), 0,
                                c->work, c->n, y, c->y32.p);
             HIP_CHECK(hipGetLastError());
-            return ICCG_OK;
+            return check_sweep_err(c);
         }
         if (r == y) return set_error(ICCG_EINVAL, "r and y must not alias");
-        return launch_sweep<true, SW_APPLY>(c, r, y, no_cg());
+        ICCG_CHECK((launch_sweep<true, SW_APPLY>(c, r, y, no_cg())));
+        return check_sweep_err(c);
     });
 }
 
@@ -1060,16 +1223,18 @@ int ic_backward(iccg_ctx *c, const double *y, double *z) {
             hipLaunchKernelGGL((k_convert<float, double>), dim3(c->vec_blocks), dim3(kVecThreads), 0,
                                c->work, c->n, c->y32.p, y);
             HIP_CHECK(hipGetLastError());
-            return launch_sweep<false, SW_APPLY>(c, c->y32.p, z, no_cg());
+            ICCG_CHECK((launch_sweep<false, SW_APPLY>(c, c->y32.p, z, no_cg())));
+            return check_sweep_err(c);
         }
-        return launch_sweep<false, SW_APPLY>(c, y, z, no_cg());
+        ICCG_CHECK((launch_sweep<false, SW_APPLY>(c, y, z, no_cg())));
+        return check_sweep_err(c);
     });
 }
 
 int iccg_spmv(iccg_ctx *c, const double *p, double *q, double *pq_host) {
     return entry(c, [&]() -> int {
         if (!p || !q || p == q) return set_error(ICCG_EINVAL, "need distinct p and q");
-        ICCG_CHECK(launch_spmv(c, SP_PLAIN, p, q, nullptr, nullptr, nullptr, nullptr));
+        ICCG_CHECK(launch_spmv(c, SP_PLAIN, p, q, nullptr, nullptr));
         if (pq_host) {
             ICCG_CHECK(launch_reduce(c, c->spmv_blocks, OP_STORE, c->b.p));
             HIP_CHECK(hipMemcpyAsync(pq_host, c->b.p, sizeof(double), hipMemcpyDeviceToHost, c->work));

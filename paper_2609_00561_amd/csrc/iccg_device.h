@@ -91,6 +91,10 @@ struct DevSweep {
     DevArray<int> scol, ssrc;
     DevArray<double> sval64;
     DevArray<float> sval32;
+    // single-launch sweep: ticket counter, per-task epoch flags, dependency lists
+    DevArray<int> epoch;            // sweep number, bumped before every launch
+    DevArray<int> flags, dep_ptr, deps, wg_task;
+    long long ndeps = 0;
 };
 
 // Per-launch HIP-event timing of an instrumented (eager) solve.
@@ -157,16 +161,17 @@ struct iccg_ctx {
     DevArray<double> inv64;
     DevArray<float> inv32;
     bool has_factor = false;
-    DevArray<double> x, r, z, q, b, y64;
-    DevArray<double> pbuf[2];       // search direction, double buffered across iterations
+    DevArray<double> x, r, z, p, q, b, y64;
     DevArray<float> y32;
     DevArray<double> part, hist;
     DevArray<DevScalars> scal;
     DevArray<int> dint;
+    DevArray<int> sweep_err;       // set by a sweep wait that exceeded its spin limit
     DevScalars *h_scal = nullptr;   // pinned
+    int h_err = 0;
     int nslices = 0;                // sliced ELL copy of A' for the SpMV
     int sell_wmax = 8;              // register slots per row in k_spmv
-    DevArray<int> sell_off, sell_w, sell_col;
+    DevArray<int> sell_order, sell_off, sell_w, sell_col;
     DevArray<double> sell_val;
     int spmv_blocks = 1, vec_blocks = 1;
     hipGraphExec_t graph = nullptr;

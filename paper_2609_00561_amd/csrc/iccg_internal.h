@@ -65,16 +65,27 @@ struct SweepPlan {
     std::vector<int> slot_src;         // CSR position of the factor value, -1 for padding
     int max_depth = 0;
     int max_width = 0;
+    // tasks of other colors whose rows this task reads (dependency lists for
+    // the single-launch sweep); all are earlier in the sweep's processing order
+    std::vector<int> dep_ptr;          // ntasks+1
+    std::vector<int> deps;
+    // launch table of the single-launch sweep: workgroup b runs task wg_task[b].
+    // Workgroups follow the processing order color by color; inside a color,
+    // the workgroups dealt to one XCD (b mod 8) get one contiguous region of
+    // the color's tasks.
+    std::vector<int> wg_task;
 };
 
 // Sliced ELL copy of A' for the SpMV: slices of 64 consecutive rows; entry k
 // of the slice's row t at slice_off[s] + k*64 + t (column -1, value 0 pads).
 struct SellMatrix {
     std::vector<int> slice_off, slice_width;   // nslices
+    std::vector<int> order;                    // launch order of the slices (see build_sell)
     std::vector<int> col;
     std::vector<double> val;
 };
-int build_sell(int n, const int *rowptr, const int *col, const double *val, SellMatrix &out);
+int build_sell(int n, const int *rowptr, const int *col, const double *val, const int *block_ptr,
+               int ncolors, const int *color_ptr, SellMatrix &out);
 
 // Builds both sweep plans from the validated permuted pattern.  tpos[k] is
 // the CSR position of the transpose of entry k.

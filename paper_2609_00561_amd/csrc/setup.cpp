@@ -119,6 +119,48 @@ int build_sweep_plan(bool forward, int n, const int *rowptr, const int *col, con
         nslots += static_cast<long long>(width) * nr;
     }
     const int ntasks = static_cast<int>(out.task_chunk_ptr.size()) - 1;
+    // dependency lists: the tasks owning the before-chunk terms of a task's rows
+    std::vector<int> task_of_row(n, -1);
+    for (int t = 0; t < ntasks; ++t)
+        for (int ch = out.task_chunk_ptr[t]; ch < out.task_chunk_ptr[t + 1]; ++ch)
+            for (int r = chunk_rows[ch].first; r < chunk_rows[ch].second; ++r) task_of_row[r] = t;
+    out.dep_ptr.assign(1, 0);
+    std::vector<int> list;
+    for (int t = 0; t < ntasks; ++t) {
+        list.clear();
+        for (int ch = out.task_chunk_ptr[t]; ch < out.task_chunk_ptr[t + 1]; ++ch)
+            for (int i = chunk_rows[ch].first; i < chunk_rows[ch].second; ++i)
+                for (int k = rowptr[i]; k < rowptr[i + 1]; ++k) {
+                    const int j = col[k];
+                    if (forward ? (j >= i) : (j <= i)) continue;
+                    const int tj = task_of_row[j];
+                    if (tj != t) list.push_back(tj);
+                }
+        std::sort(list.begin(), list.end());
+        list.erase(std::unique(list.begin(), list.end()), list.end());
+        for (int d : list)
+            if (forward ? (d > t) : (d < t))
+                return set_error(ICCG_EBADORDER, "a sweep dependency points forward in processing order");
+        out.deps.insert(out.deps.end(), list.begin(), list.end());
+        out.dep_ptr.push_back(static_cast<int>(out.deps.size()));
+    }
+    // launch table
+    out.wg_task.assign(ntasks, -1);
+    int B = 0;
+    for (int step = 0; step < ncolors; ++step) {
+        const int c = forward ? step : ncolors - 1 - step;
+        const int t0 = out.color_task_ptr[c], t1 = out.color_task_ptr[c + 1], T = t1 - t0;
+        int cnt[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        for (int b = B; b < B + T; ++b) cnt[b & 7]++;
+        int next[8];
+        int start = t0;
+        for (int x = 0; x < 8; ++x) {
+            next[x] = start;
+            start += cnt[x];
+        }
+        for (int b = B; b < B + T; ++b) out.wg_task[b] = next[b & 7]++;
+        B += T;
+    }
     out.tasks.resize(ntasks);
     for (int t = 0; t < ntasks; ++t) {
         TaskRec &tr = out.tasks[t];
@@ -131,7 +173,33 @@ int build_sweep_plan(bool forward, int n, const int *rowptr, const int *col, con
     return ICCG_OK;
 }
 
-int build_sell(int n, const int *rowptr, const int *col, const double *val, SellMatrix &out) {
+// Launch order of the slices: the k-th eighth of every color's rows goes to
+// the k-th eighth of the launch, so the workgroups that one XCD runs cover the
+// same region of the domain in every color, and the values they gather from
+// the other colors share that XCD's L2.
+static std::vector<int> slice_launch_order(int n, int ns, const int *block_ptr, int ncolors,
+                                           const int *color_ptr) {
+    std::vector<int> c_row0(ncolors), c_rows(ncolors);
+    for (int c = 0; c < ncolors; ++c) {
+        c_row0[c] = block_ptr[color_ptr[c]];
+        c_rows[c] = block_ptr[color_ptr[c + 1]] - c_row0[c];
+    }
+    std::vector<long long> key(ns);
+    int c = 0;
+    for (int s = 0; s < ns; ++s) {
+        const int r = std::min(n - 1, s * kChunkRows);
+        while (c + 1 < ncolors && r >= c_row0[c + 1]) ++c;
+        const int bucket = std::min(7, static_cast<int>(8LL * (r - c_row0[c]) / std::max(1, c_rows[c])));
+        key[s] = (static_cast<long long>(bucket) << 40) | (static_cast<long long>(c) << 32) | s;
+    }
+    std::vector<int> order(ns);
+    for (int s = 0; s < ns; ++s) order[s] = s;
+    std::sort(order.begin(), order.end(), [&](int a, int b) { return key[a] < key[b]; });
+    return order;
+}
+
+int build_sell(int n, const int *rowptr, const int *col, const double *val, const int *block_ptr,
+               int ncolors, const int *color_ptr, SellMatrix &out) {
     const int ns = (n + kChunkRows - 1) / kChunkRows;
     out.slice_off.assign(ns, 0);
     out.slice_width.assign(ns, 0);
@@ -156,6 +224,7 @@ int build_sell(int n, const int *rowptr, const int *col, const double *val, Sell
                 out.val[slot] = val[k];
             }
         }
+    out.order = slice_launch_order(n, ns, block_ptr, ncolors, color_ptr);
     return ICCG_OK;
 }
 

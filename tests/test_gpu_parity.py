@@ -337,3 +337,24 @@ def test_fp32_solve_converges(case):
     err = np.linalg.norm(x - ref.x) / np.linalg.norm(ref.x)
     print(case, "fp32 iters", res["iters"], "fp64 oracle iters", ref.iters, "x rel diff", err)
     assert res["iters"] <= ref.iters * 1.2 + 5
+
+
+@pytest.mark.parametrize("case", [CASES[1], CASES[3], CASES[6], CASES[7]], ids=_ids)
+def test_single_launch_sweep_identical_to_per_color(case):
+    """The single-launch sweep (per-task dependency waits) computes the same
+    per-row terms as one launch per color: outputs and solves are bit-identical."""
+    cs = _case(*case)
+    Ap = cs[4]
+    r = np.random.default_rng(8).standard_normal(Ap.n)
+    outs, sols = [], []
+    for mode in ("per_color", "single"):
+        with _ctx(cs, sweep_launch=mode) as ctx:
+            zd = torch.zeros(Ap.n, dtype=torch.float64, device="cuda")
+            for _ in range(3):                      # repeated launches reuse the epoch flags
+                ctx.ic_apply(_dev(r), zd)
+            outs.append(_host(zd))
+            xd = torch.zeros(Ap.n, dtype=torch.float64, device="cuda")
+            res = ctx.solve(_dev(cs[6]), xd)
+            sols.append((res["iters"], _host(xd)))
+    assert np.array_equal(outs[0], outs[1])
+    assert sols[0][0] == sols[1][0] and np.array_equal(sols[0][1], sols[1][1])
