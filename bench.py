@@ -30,9 +30,136 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 
+# HBM traffic of the timed kernels, from two rocprofv3 --pmc passes (FETCH_SIZE,
+# then WRITE_SIZE) over `bench.py --traffic-run`, scaled by what the same
+# counters read for a plain streaming kernel of known size (torch.neg over
+# 2^26 doubles: 512 MiB read, 512 MiB written).  The summary records a hash
+# of the sources that shape those kernels; a stale summary gives null.
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_sweep_spmv_poisson7_128_abmc16.md")
+TRAFFIC_SOURCES = ["paper_2609_00561_amd/csrc/iccg.hip", "paper_2609_00561_amd/csrc/iccg_device.h",
+                   "paper_2609_00561_amd/csrc/iccg_internal.h", "paper_2609_00561_amd/csrc/setup.cpp"]
+CALIB_ELEMS = 1 << 26
+KERNEL_CLASSES = {            # rocprofv3 kernel name pattern -> report name
+    "k_sweep(forward)": r"k_sweep<double, true, \d+, 1,",
+    "k_sweep(backward)": r"k_sweep<double, false, \d+, 2,",
+    "k_spmv": r"k_spmv<0,",
+    "calibration": r"neg",
+}
+
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for rel in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def _counter_rows(directory):
+    """(kernel name, counter value) per dispatch from a rocprofv3 csv pass."""
+    import csv
+    import glob
+    files = glob.glob(os.path.join(directory, "**", "*counter_collection.csv"), recursive=True)
+    if not files:
+        raise SystemExit(f"no counter_collection.csv under {directory}")
+    rows = []
+    for fn in files:
+        with open(fn, newline="") as f:
+            for r in csv.DictReader(f):
+                rows.append((r["Kernel_Name"], r["Counter_Name"], float(r["Counter_Value"])))
+    return rows
+
+
+def traffic_summary(fetch_dir, write_dir, command_fetch, command_write):
+    """Per-dispatch FETCH_SIZE / WRITE_SIZE of the timed kernels, scaled by the
+    calibration kernel, written to the committed summary."""
+    import re
+    calib_bytes = 8.0 * CALIB_ELEMS
+    per = {}
+    for counter, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
+        for name, cname, v in _counter_rows(d):
+            if cname != counter:
+                continue
+            for cls, pat in KERNEL_CLASSES.items():
+                if re.search(pat, name):
+                    per.setdefault((cls, counter), []).append(v)
+    lines = ["# HBM traffic per dispatch: ICCG kernels on poisson7_128 (ABMC s=16)", "",
+             "Counters in KiB per dispatch, averaged over the dispatches of one class; the",
+             "scale factor is the known bytes of the calibration kernel (torch.neg over",
+             f"{CALIB_ELEMS} doubles: {calib_bytes:.0f} B read, {calib_bytes:.0f} B written) divided",
+             "by what the counter reads for it.", "",
+             f"FETCH pass: `{command_fetch}`", "",
+             f"WRITE pass: `{command_write}`", "",
+             f"source-hash: {source_hash()}", "",
+             "| kernel | dispatches | FETCH_SIZE KiB | WRITE_SIZE KiB | scaled read B | scaled write B |",
+             "|---|---|---|---|---|---|"]
+    cf = calib_bytes / (1024.0 * np.mean(per[("calibration", "FETCH_SIZE")]))
+    cw = calib_bytes / (1024.0 * np.mean(per[("calibration", "WRITE_SIZE")]))
+    result = {}
+    for cls in KERNEL_CLASSES:
+        f = per.get((cls, "FETCH_SIZE"), [])
+        w = per.get((cls, "WRITE_SIZE"), [])
+        if not f or not w:
+            continue
+        rb = 1024.0 * float(np.mean(f)) * cf
+        wb = 1024.0 * float(np.mean(w)) * cw
+        result[cls] = rb + wb
+        lines.append(f"| {cls} | {len(f)} | {np.mean(f):.1f} | {np.mean(w):.1f} | {rb:.0f} | {wb:.0f} |")
+    lines += ["", f"scale: FETCH x{cf:.4f}, WRITE x{cw:.4f}", ""]
+    for cls, v in result.items():
+        if cls != "calibration":
+            lines.append(f"traffic-bytes-per-launch {cls} {v:.0f}")
+    os.makedirs(os.path.dirname(TRAFFIC_FILE), exist_ok=True)
+    with open(TRAFFIC_FILE, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+def traffic_for(kernel):
+    """Scaled HBM bytes per launch of `kernel` from the committed summary, or
+    None when it is missing or was taken from other kernel sources."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            text = fh.read().splitlines()
+    except OSError:
+        return None
+    if f"source-hash: {source_hash()}" not in text:
+        return None
+    for ln in text:
+        parts = ln.split()
+        if len(parts) == 3 and parts[0] == "traffic-bytes-per-launch" and parts[1] == kernel:
+            return float(parts[2])
+    return None
+
+
+def traffic_run(args):
+    """The program the --pmc passes profile: the calibration kernel, then 30
+    iterations of the timed solve configuration."""
+    import torch
+    import synth
+    from paper_2609_00561_amd import iccg
+    x = torch.ones(CALIB_ELEMS, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        torch.neg(x, out=y)
+    torch.cuda.synchronize()
+    del x, y
+    A, b = synth.workload(args.workload, args.seed)
+    s = int(args.block_sizes.split(",")[0])
+    order = iccg.iccg_order_abmc(A, s)
+    rp, cl, vl = iccg.iccg_permute(A, order.perm)
+    with iccg.Context(rp, cl, vl, order.block_ptr, order.color_ptr) as ctx:
+        ctx.ic0_factor()
+        bd = torch.tensor(b[order.perm], device="cuda")
+        xd = torch.zeros(A.n, dtype=torch.float64, device="cuda")
+        r = ctx.solve(bd, xd, tol=args.tol, maxit=30, raise_on_noconv=False)
+        torch.cuda.synchronize()
+    log(f"[traffic-run] done: {r['iters']} iterations")
 
 
 def parse():
@@ -51,11 +178,18 @@ def parse():
     ap.add_argument("--learned-matrices", type=int, default=256)
     ap.add_argument("--learned-epochs", type=int, default=3)
     ap.add_argument("--seed", type=int, default=42)
+    ap.add_argument("--traffic-run", action="store_true",
+                    help="run only the program profiled by the --pmc traffic passes")
+    ap.add_argument("--traffic-summary", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "CMD_FETCH", "CMD_WRITE"),
+                    help="write the traffic summary from two rocprofv3 csv passes (no GPU)")
     return ap.parse_args()
 
 
 def main():
     args = parse()
+    if args.traffic_summary:
+        traffic_summary(*args.traffic_summary)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
               "sharding of this method is a design note, not a built path.", file=sys.stderr)
@@ -69,6 +203,9 @@ def main():
         sys.exit(1)
     iccg.load()
     dev = torch.device("cuda:0")
+    if args.traffic_run:
+        traffic_run(args)
+        return
 
     t0 = time.time()
     A, b = synth.workload(args.workload, args.seed)
@@ -144,23 +281,29 @@ def main():
     # instrumented solve: per-launch HIP events on the library's stream
     prof = ctx.profile_solve(torch.tensor(bp, device=dev),
                              torch.zeros(A.n, dtype=torch.float64, device=dev), tol=args.tol)
-    n_apply = prof["iters"] + 1                         # sweeps per direction in one solve
+    # algorithmic bytes per sweep: the substitution's compulsory bytes (library
+    # info) plus the fused CG work: the forward sweep also reads x, p, q and
+    # writes x, r (40 B/row); the backward sweep also reads r for (r, z)
     sweep_bytes = info["sweep_bytes"]
+    fwd_bytes = sweep_bytes + 40.0 * A.n
+    bwd_bytes = sweep_bytes + 8.0 * A.n
     fwd_launch_ms = prof["fwd_ms"] / max(prof["fwd_launches"], 1)
     bwd_launch_ms = prof["bwd_ms"] / max(prof["bwd_launches"], 1)
     spmv_launch_ms = prof["spmv_ms"] / max(prof["spmv_launches"], 1)
     nc = info["ncolors"]
-    fwd_gbs = (sweep_bytes / nc) / (fwd_launch_ms * 1e-3) / 1e9
-    bwd_gbs = (sweep_bytes / nc) / (bwd_launch_ms * 1e-3) / 1e9
+    fwd_gbs = (fwd_bytes / nc) / (fwd_launch_ms * 1e-3) / 1e9
+    bwd_gbs = (bwd_bytes / nc) / (bwd_launch_ms * 1e-3) / 1e9
     spmv_gbs = info["spmv_bytes"] / (spmv_launch_ms * 1e-3) / 1e9
-    kernels = {"k_sweep(forward)": (prof["fwd_ms"], fwd_gbs, fwd_launch_ms, sweep_bytes / nc),
-               "k_sweep(backward)": (prof["bwd_ms"], bwd_gbs, bwd_launch_ms, sweep_bytes / nc),
+    kernels = {"k_sweep(forward)": (prof["fwd_ms"], fwd_gbs, fwd_launch_ms, fwd_bytes / nc),
+               "k_sweep(backward)": (prof["bwd_ms"], bwd_gbs, bwd_launch_ms, bwd_bytes / nc),
                "k_spmv": (prof["spmv_ms"], spmv_gbs, spmv_launch_ms, info["spmv_bytes"])}
     dom = max(kernels, key=lambda k: kernels[k][0])
+    traffic = traffic_for(dom) if s_best == 16 and args.workload == "poisson7_128" else None
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(kernels[dom][1], 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(kernels[dom][1] / HBM_PEAK_GBS, 4), "traffic": None,
-                "bytes_per_launch": kernels[dom][3],
+                "frac": round(kernels[dom][1] / HBM_PEAK_GBS, 4),
+                "traffic": round(traffic) if traffic is not None else None,
+                "bytes_per_launch": round(kernels[dom][3]),
                 "avg_launch_us": round(kernels[dom][2] * 1e3, 3)}
 
     out = {

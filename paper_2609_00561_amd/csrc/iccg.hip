@@ -655,11 +655,13 @@ int launch_sweep_t(iccg_ctx *c, const void *in, void *out, const CgArgs &cg) {
         return ICCG_OK;
     }
 #define SWEEP_ARGS a.tasks, a.chunks, a.meta, a.scol, a.sval, a.inv, t0, t1 - t0, pin, pout, cg
+    if (c->prof) c->prof->begin(c->work);
+    int launched = 0;
     for (int step = 0; step < c->ncolors; ++step) {
         const int col = FWD ? step : c->ncolors - 1 - step;
         const int t0 = d.color_task_ptr[col], t1 = d.color_task_ptr[col + 1];
         if (t1 == t0) continue;
-        if (c->prof) c->prof->begin(c->work);
+        ++launched;
         const dim3 grid(t1 - t0), block(64);
         switch (d.kmax) {
             case 4: hipLaunchKernelGGL((k_sweep<F, FWD, 4, MODE, TIn, TOut>), grid, block, 0, c->work, SWEEP_ARGS); break;
@@ -667,8 +669,8 @@ int launch_sweep_t(iccg_ctx *c, const void *in, void *out, const CgArgs &cg) {
             case 16: hipLaunchKernelGGL((k_sweep<F, FWD, 16, MODE, TIn, TOut>), grid, block, 0, c->work, SWEEP_ARGS); break;
             default: hipLaunchKernelGGL((k_sweep<F, FWD, 32, MODE, TIn, TOut>), grid, block, 0, c->work, SWEEP_ARGS); break;
         }
-        if (c->prof) c->prof->end(c->work, FWD ? PK_FWD : PK_BWD);
     }
+    if (c->prof) c->prof->end(c->work, FWD ? PK_FWD : PK_BWD, launched);
 #undef SWEEP_ARGS
     HIP_CHECK(hipGetLastError());
     return ICCG_OK;

@@ -100,9 +100,13 @@ struct DevSweep {
 // Per-launch HIP-event timing of an instrumented (eager) solve.
 enum ProfKind : int { PK_SPMV = 0, PK_FWD = 1, PK_BWD = 2, PK_COUNT = 3 };
 
+// Device time per kind of kernel: one event pair brackets each run of
+// back-to-back launches of one kind (all colors of a sweep, one SpMV), so the
+// bracket adds no gap between the kernels it times.
 struct Profiler {
     std::vector<hipEvent_t> pool;
     std::vector<int> kinds;       // kind of each recorded pair
+    std::vector<int> counts;      // launches inside each recorded pair
     size_t used = 0;              // events used in the current round
     double ms[PK_COUNT] = {0, 0, 0};
     long long launches[PK_COUNT] = {0, 0, 0};
@@ -121,10 +125,11 @@ struct Profiler {
         hipEvent_t e = next();
         if (e) (void)hipEventRecord(e, s);
     }
-    void end(hipStream_t s, int kind) {
+    void end(hipStream_t s, int kind, int count = 1) {
         hipEvent_t e = next();
         if (e) (void)hipEventRecord(e, s);
         kinds.push_back(kind);
+        counts.push_back(count);
     }
     // after the stream has drained: fold the recorded pairs into the totals
     void harvest() {
@@ -132,10 +137,11 @@ struct Profiler {
             float t = 0.0f;
             if (hipEventElapsedTime(&t, pool[2 * k], pool[2 * k + 1]) == hipSuccess) {
                 ms[kinds[k]] += t;
-                launches[kinds[k]] += 1;
+                launches[kinds[k]] += counts[k];
             }
         }
         kinds.clear();
+        counts.clear();
         used = 0;
     }
 };
