@@ -341,31 +341,76 @@ struct CgArgs {
 
 // One chunk of a task: see k_sweep.
 struct NoWait {
-    __device__ void operator()() const {}
+    __device__ int pre() const { return 0; }
+    __device__ void operator()(int) const {}
 };
 
-// Device-scope (agent) relaxed accesses: they bypass the non-coherent caches,
-// so values written by one XCD are read correctly by another once the writer
-// has waited for its stores and raised a flag.  Used for the values that cross
-// tasks inside one single-launch sweep.
-template <typename T>
-__device__ __forceinline__ T load_coherent(const T *p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+// Plain accesses: the per-color launches, where every value a task reads was
+// written by an earlier launch or by the same wavefront.
+struct PlainMem {
+    template <typename T>
+    __device__ __forceinline__ T gather(const T *out, int j) const { return out[j]; }
+    template <typename T>
+    __device__ __forceinline__ void store(T *out, int i, T v, uint32_t) const { out[i] = v; }
+};
+
+// Raw buffer accesses with an explicit cache policy (gfx950 CPol bits: 1 = sc0,
+// 2 = nt, 16 = sc1).  Loads with sc0|nt miss in the CU's L1 and are served by
+// the XCD's L2, which holds every store of that XCD's waves once the storing
+// wave's vmcnt has drained; sc0 alone is not enough (a stale L1 line can keep
+// serving it).  sc1 loads are coherent across XCDs.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void *p, long long bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), 0, static_cast<int>(bytes),
+                                             0x00020000);
 }
-template <typename T>
-__device__ __forceinline__ void store_coherent(T *p, T v) {
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+template <int AUX>
+__device__ __forceinline__ double buf_load(__amdgpu_buffer_rsrc_t r, int j, double) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, j * 8, 0, AUX));
 }
+template <int AUX>
+__device__ __forceinline__ float buf_load(__amdgpu_buffer_rsrc_t r, int j, float) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, j * 4, 0, AUX));
+}
+template <int AUX>
+__device__ __forceinline__ int buf_load_i32(__amdgpu_buffer_rsrc_t r, int j) {
+    return static_cast<int>(__builtin_amdgcn_raw_buffer_load_b32(r, j * 4, 0, AUX));
+}
+constexpr int kCpolL2 = 3;     // sc0 | nt
+constexpr int kCpolSc1 = 16;
+
+// Accesses of the single-launch sweep.  A task whose dependencies all lie in
+// its own region reads them from its XCD's L2 (sc0|nt); a task with a dependency
+// in another region reads every before-chunk value coherently across XCDs
+// (sc1).  Rows that such tasks read carry the export bit and are written
+// through to memory (sc1 stores); on the task's last chunk that write-through
+// is deferred until the task has signalled its own region.
+struct FlowMem {
+    __amdgpu_buffer_rsrc_t rs;
+    bool remote;
+    bool defer_export;
+    template <typename T>
+    __device__ __forceinline__ T gather(const T *, int j) const {
+        return remote ? buf_load<kCpolSc1>(rs, j, T()) : buf_load<kCpolL2>(rs, j, T());
+    }
+    template <typename T>
+    __device__ __forceinline__ void store(T *out, int i, T v, uint32_t m) const {
+        if ((m & kMetaExport) && !defer_export)
+            __hip_atomic_store(out + i, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        else
+            out[i] = v;
+    }
+};
 
 template <typename F, bool FWD, int KMAX, int MODE, typename TIn, typename TOut, class Wait = NoWait,
-          bool COH = false>
+          class Mem = PlainMem>
 __device__ __forceinline__ void sweep_chunk(const Chunk &ch, const uint32_t *__restrict__ meta,
                                             const int *__restrict__ scol,
                                             const F *__restrict__ sval,
                                             const F *__restrict__ inv,
                                             const TIn *__restrict__ in, TOut *__restrict__ out,
                                             const CgArgs &cg, double alpha, F *ys, double &dacc,
-                                            const Wait &wait = Wait()) {
+                                            const Wait &wait, const Mem &mem, F &y_out,
+                                            uint32_t &m_out) {
     const int t = threadIdx.x;
     const int nr = ch.shape & 0xffff, W = ch.shape >> 16;
     const bool active = t < nr;
@@ -376,6 +421,8 @@ __device__ __forceinline__ void sweep_chunk(const Chunk &ch, const uint32_t *__r
     uint32_t m = 0;
     F s = F(0), dinv = F(0);
     double rd = 0.0;
+    // the first dependency a lane waits for, ahead of the chunk's loads
+    const int pre = wait.pre();
     if (active) {
         // every independent load of the chunk first, so they overlap
 #pragma unroll
@@ -399,25 +446,21 @@ __device__ __forceinline__ void sweep_chunk(const Chunk &ch, const uint32_t *__r
         if (MODE == SW_DOT_BWD) rd = cg.rdot[i];
     }
     // values of other tasks are read only after their producers published them
-    wait();
-    const int ne = m & 0xffffu, ni = (m >> 16) & 0xffu, lev = m >> 24;
+    wait(pre);
+    const int ne = m & kMetaNextMask, ni = (m >> 16) & 0xffu, lev = m >> 24;
     if (active) {
         // all gathers at once (the chunk width is uniform); slots that are not
         // before-chunk terms read a harmless valid address and are discarded
         F g[KMAX];
 #pragma unroll
         for (int k = 0; k < KMAX; ++k)
-            if (k < W) {
-                const TOut *src = out + (cc[k] < 0 ? 0 : cc[k]);
-                g[k] = static_cast<F>(COH ? load_coherent(src) : *src);
-            }
+            if (k < W) g[k] = static_cast<F>(mem.gather(out, cc[k] < 0 ? 0 : cc[k]));
 #pragma unroll
         for (int k = 0; k < KMAX; ++k)
             if (k < W) s = (k < ne) ? s - vv[k] * g[k] : s;
         for (int k = KMAX; k < ne; ++k) {
             const int sl = base + k * nr;
-            const TOut *src = out + scol[sl];
-            s -= sval[sl] * static_cast<F>(COH ? load_coherent(src) : *src);
+            s -= sval[sl] * static_cast<F>(mem.gather(out, scol[sl]));
         }
     }
     for (int L = 0; L < ch.depth; ++L) {
@@ -433,12 +476,14 @@ __device__ __forceinline__ void sweep_chunk(const Chunk &ch, const uint32_t *__r
         }
         __syncthreads();
     }
+    F yv = F(0);
     if (active) {
-        const F yv = ys[t];
-        if (COH) store_coherent(out + i, static_cast<TOut>(yv));
-        else out[i] = static_cast<TOut>(yv);
+        yv = ys[t];
+        mem.store(out, i, static_cast<TOut>(yv), m);
         if (MODE == SW_DOT_BWD) dacc += rd * static_cast<double>(yv);
     }
+    y_out = yv;
+    m_out = m;
 }
 
 // FWD: y_i = (r_i - sum_{j<i} L_ij y_j) / L_ii over the rows of one color.
@@ -463,14 +508,17 @@ __global__ __launch_bounds__(64) void k_sweep(const TaskRec *__restrict__ tasks,
     const TaskRec tr = tasks[task];
     const double alpha = (MODE == SW_CG_FWD) ? cg.sc->alpha : 0.0;
     double dacc = 0.0;
+    F yv;
+    uint32_t m;
     sweep_chunk<F, FWD, KMAX, MODE, TIn, TOut>(tr.first, meta, scol, sval, inv, in, out, cg, alpha,
-                                               ys, dacc);
-    for (int q = 1; q < tr.nchunks; ++q) {
+                                               ys, dacc, NoWait(), PlainMem(), yv, m);
+    const int nchunks = tr.c1 - tr.c0;
+    for (int q = 1; q < nchunks; ++q) {
         // later chunks of this task read earlier chunks' results from memory
         __syncthreads();
         const Chunk ch = chunks[FWD ? tr.c0 + q : tr.c1 - 1 - q];
         sweep_chunk<F, FWD, KMAX, MODE, TIn, TOut>(ch, meta, scol, sval, inv, in, out, cg, alpha,
-                                                   ys, dacc);
+                                                   ys, dacc, NoWait(), PlainMem(), yv, m);
     }
     if (MODE != SW_APPLY) {
         const double tsum = wave_sum(dacc);
@@ -482,92 +530,142 @@ __global__ __launch_bounds__(64) void k_sweep(const TaskRec *__restrict__ tasks,
 // runs task wg_task[b]; the table lists the tasks in processing order
 // (forward: colors ascending, backward: descending), so every task a
 // workgroup waits for belongs to a workgroup with a smaller index, which the
-// in-order dispatch has already started; that guarantees progress.  A task
-// waits for the tasks it reads (its dependency list) by polling their flags,
-// which hold the number (epoch) of the sweep that last completed them; a
-// finished task publishes its results with an agent-scope release store of
-// the current epoch.  The epoch is bumped by a one-thread kernel before every
-// launch, so flags are never reset.  A wait that exceeds the spin limit sets
-// *err and continues, so every wavefront always exits.
-struct SyncArgs {
+// in-order dispatch has already started; that guarantees progress.
+//
+// Workgroups are dealt to the XCDs round robin, so the workgroups with one
+// value of b mod 8 (one region of the domain in every color) share an XCD
+// and its L2.  A finished task raises two flags holding (epoch << 4 | XCC id):
+//   flag_loc, after its stores have reached L2 (read by same-region tasks
+//             through L2), and
+//   flag_rem, after its exported rows have been written through to memory
+//             (read coherently by tasks that have a dependency elsewhere).
+// A same-region waiter checks that the producer ran on its own XCD; if the
+// round-robin placement ever failed, the sweep reports an error instead of
+// reading a value that might not be visible.  The epoch is bumped by a
+// one-thread kernel before every launch, so flags are never reset between
+// sweeps.  A wait that exceeds the spin limit sets *err and continues, so
+// every wavefront always exits.
+struct FlowArgs {
     const int *epoch;
-    int *flags;
+    int *flag_loc;
+    int *flag_rem;
     const int *dep_ptr;
     const int *deps;
     const int *wg_task;
+    int ntasks;
     int spin_limit;
-    int *err;
+    int *err;            // 1: spin limit, 2: placement
 };
 
 __global__ void k_bump_epoch(int *epoch, const DevScalars *sc) {
     if (threadIdx.x == 0 && blockIdx.x == 0 && !(sc && sc->done != DONE_RUNNING)) *epoch += 1;
 }
 
-struct DepWait {
-    const SyncArgs *sy;
-    int task, epoch;
-    __device__ void operator()() const {
-        // one lane per dependency polls its flag
-        const int d0 = sy->dep_ptr[task], d1 = sy->dep_ptr[task + 1];
-        for (int d = d0 + static_cast<int>(threadIdx.x); d < d1; d += 64) {
-            const int *f = sy->flags + sy->deps[d];
+__device__ __forceinline__ int xcc_id() {
+    int v;
+    asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID)" : "=s"(v));
+    return v & 15;
+}
+
+struct FlowWait {
+    const FlowArgs *fa;
+    __amdgpu_buffer_rsrc_t rs_loc;
+    int task, epoch, xcc;
+    int d0, nd;
+    bool remote;
+    __device__ int pre() const {
+        const int l = static_cast<int>(threadIdx.x);
+        return l < nd ? fa->deps[d0 + l] : 0;
+    }
+    // one lane per dependency polls its flag
+    __device__ void operator()(int first) const {
+        for (int l = static_cast<int>(threadIdx.x); l < nd; l += 64) {
+            const int dep = l < 64 ? first : fa->deps[d0 + l];
             int spins = 0;
-            while (__hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < epoch) {
+            while (true) {
+                const int v = remote ? __hip_atomic_load(fa->flag_rem + dep, __ATOMIC_RELAXED,
+                                                         __HIP_MEMORY_SCOPE_AGENT)
+                                     : buf_load_i32<kCpolL2>(rs_loc, dep);
+                if ((v >> 4) >= epoch) {
+                    if (!remote && (v & 15) != xcc)
+                        __hip_atomic_store(fa->err, 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    break;
+                }
                 __builtin_amdgcn_s_sleep(1);
                 ++spins;
-                // after any timeout every other wait gives up at once
+                // after any failure every other wait gives up at once
                 if ((spins & 255) == 0 &&
-                    __hip_atomic_load(sy->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+                    __hip_atomic_load(fa->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
                     break;
-                if (spins > sy->spin_limit) {
-                    __hip_atomic_store(sy->err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (spins > fa->spin_limit) {
+                    __hip_atomic_store(fa->err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     break;
                 }
             }
         }
-        // the gathers that follow are device-scope loads issued after the
-        // flags were seen, so they read the producers' device-scope stores
-        __syncthreads();
+        // the wavefront's lanes reconverge here; the gathers that follow are
+        // issued after every flag was seen
     }
 };
 
 template <typename F, bool FWD, int KMAX, int MODE, typename TIn, typename TOut>
-__global__ __launch_bounds__(64) void k_sweep_dep(const TaskRec *__restrict__ tasks,
-                                                  const Chunk *__restrict__ chunks,
-                                                  const uint32_t *__restrict__ meta,
-                                                  const int *__restrict__ scol,
-                                                  const F *__restrict__ sval,
-                                                  const F *__restrict__ inv, SyncArgs sy,
-                                                  const TIn *__restrict__ in,
-                                                  TOut *__restrict__ out, CgArgs cg) {
+__global__ __launch_bounds__(64) void k_sweep_flow(const TaskRec *__restrict__ tasks,
+                                                   const Chunk *__restrict__ chunks,
+                                                   const uint32_t *__restrict__ meta,
+                                                   const int *__restrict__ scol,
+                                                   const F *__restrict__ sval,
+                                                   const F *__restrict__ inv, FlowArgs fa, int n,
+                                                   const TIn *__restrict__ in,
+                                                   TOut *__restrict__ out, CgArgs cg) {
     if (cg.sc && cg.sc->done != DONE_RUNNING) return;
     __shared__ F ys[kChunkRows];
-    const int epoch = *sy.epoch;
-    const int task = sy.wg_task[blockIdx.x];
+    const int epoch = *fa.epoch;
+    const int task = fa.wg_task[blockIdx.x];
+    const int xcc = xcc_id();
     const TaskRec tr = tasks[task];
+    const int kind = tr.kind_ndeps & 3, nchunks = tr.c1 - tr.c0;
+    const bool remote = (kind & kTaskRemote) != 0;
     const double alpha = (MODE == SW_CG_FWD) ? cg.sc->alpha : 0.0;
     double dacc = 0.0;
-    const DepWait wait{&sy, task, epoch};
-    sweep_chunk<F, FWD, KMAX, MODE, TIn, TOut, DepWait, true>(tr.first, meta, scol, sval, inv, in,
-                                                             out, cg, alpha, ys, dacc, wait);
-    for (int q = 1; q < tr.nchunks; ++q) {
+    const __amdgpu_buffer_rsrc_t rs_out = make_rsrc(out, static_cast<long long>(n) * sizeof(TOut));
+    const FlowWait wait{&fa, make_rsrc(fa.flag_loc, 4LL * fa.ntasks), task, epoch, xcc,
+                        tr.dep0, tr.kind_ndeps >> 2, remote};
+    F yv;
+    uint32_t m;
+    sweep_chunk<F, FWD, KMAX, MODE, TIn, TOut>(tr.first, meta, scol, sval, inv, in, out, cg, alpha,
+                                               ys, dacc, wait, FlowMem{rs_out, remote, nchunks == 1},
+                                               yv, m);
+    for (int q = 1; q < nchunks; ++q) {
         __builtin_amdgcn_s_waitcnt(0);   // this chunk's stores are complete before they are read
         __syncthreads();
         const Chunk ch = chunks[FWD ? tr.c0 + q : tr.c1 - 1 - q];
-        sweep_chunk<F, FWD, KMAX, MODE, TIn, TOut, NoWait, true>(ch, meta, scol, sval, inv, in, out,
-                                                                 cg, alpha, ys, dacc);
+        sweep_chunk<F, FWD, KMAX, MODE, TIn, TOut>(ch, meta, scol, sval, inv, in, out, cg, alpha,
+                                                   ys, dacc, NoWait(),
+                                                   FlowMem{rs_out, remote, q == nchunks - 1}, yv, m);
     }
     if (MODE != SW_APPLY) {
         const double tsum = wave_sum(dacc);
         if (threadIdx.x == 0) cg.part[task] = tsum;
     }
-    // publish: this wavefront's device-scope stores are complete before the
-    // flag is raised
+    const int word = (epoch << 4) | xcc;
+    // signal the region: every store of this wavefront has reached L2
     __builtin_amdgcn_s_waitcnt(0);
     __atomic_signal_fence(__ATOMIC_SEQ_CST);
-    __syncthreads();
     if (threadIdx.x == 0)
-        __hip_atomic_store(sy.flags + task, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(fa.flag_loc + task, word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    if (kind & kTaskExports) {
+        // then write the last chunk's exported rows through and signal the
+        // other regions
+        const int nr = (FWD ? chunks[tr.c1 - 1] : chunks[tr.c0]).shape & 0xffff;
+        const int row0 = (FWD ? chunks[tr.c1 - 1] : chunks[tr.c0]).row0;
+        if (static_cast<int>(threadIdx.x) < nr && (m & kMetaExport))
+            __hip_atomic_store(out + row0 + threadIdx.x, static_cast<TOut>(yv), __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        __builtin_amdgcn_s_waitcnt(0);
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        if (threadIdx.x == 0)
+            __hip_atomic_store(fa.flag_rem + task, word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
 }
 
 namespace {
@@ -631,25 +729,27 @@ int launch_sweep_t(iccg_ctx *c, const void *in, void *out, const CgArgs &cg) {
     const TIn *pin = static_cast<const TIn *>(in);
     TOut *pout = static_cast<TOut *>(out);
     if (c->opt.sweep_launch == 1) {
-        SyncArgs sy;
-        sy.epoch = d.epoch.p;
-        sy.flags = d.flags.p;
-        sy.dep_ptr = d.dep_ptr.p;
-        sy.deps = d.deps.p;
-        sy.wg_task = d.wg_task.p;
-        sy.spin_limit = 1 << 18;
-        sy.err = c->sweep_err.p;
+        FlowArgs fa;
+        fa.epoch = d.epoch.p;
+        fa.flag_loc = d.flag_loc.p;
+        fa.flag_rem = d.flag_rem.p;
+        fa.dep_ptr = d.dep_ptr.p;
+        fa.deps = d.deps.p;
+        fa.wg_task = d.wg_task.p;
+        fa.ntasks = d.ntasks;
+        fa.spin_limit = 1 << 18;
+        fa.err = c->sweep_err.p;
         hipLaunchKernelGGL(k_bump_epoch, dim3(1), dim3(64), 0, c->work, d.epoch.p, cg.sc);
         if (c->prof) c->prof->begin(c->work);
         const dim3 grid(d.ntasks), block(64);
-#define DEP_ARGS a.tasks, a.chunks, a.meta, a.scol, a.sval, a.inv, sy, pin, pout, cg
+#define FLOW_ARGS a.tasks, a.chunks, a.meta, a.scol, a.sval, a.inv, fa, c->n, pin, pout, cg
         switch (d.kmax) {
-            case 4: hipLaunchKernelGGL((k_sweep_dep<F, FWD, 4, MODE, TIn, TOut>), grid, block, 0, c->work, DEP_ARGS); break;
-            case 8: hipLaunchKernelGGL((k_sweep_dep<F, FWD, 8, MODE, TIn, TOut>), grid, block, 0, c->work, DEP_ARGS); break;
-            case 16: hipLaunchKernelGGL((k_sweep_dep<F, FWD, 16, MODE, TIn, TOut>), grid, block, 0, c->work, DEP_ARGS); break;
-            default: hipLaunchKernelGGL((k_sweep_dep<F, FWD, 32, MODE, TIn, TOut>), grid, block, 0, c->work, DEP_ARGS); break;
+            case 4: hipLaunchKernelGGL((k_sweep_flow<F, FWD, 4, MODE, TIn, TOut>), grid, block, 0, c->work, FLOW_ARGS); break;
+            case 8: hipLaunchKernelGGL((k_sweep_flow<F, FWD, 8, MODE, TIn, TOut>), grid, block, 0, c->work, FLOW_ARGS); break;
+            case 16: hipLaunchKernelGGL((k_sweep_flow<F, FWD, 16, MODE, TIn, TOut>), grid, block, 0, c->work, FLOW_ARGS); break;
+            default: hipLaunchKernelGGL((k_sweep_flow<F, FWD, 32, MODE, TIn, TOut>), grid, block, 0, c->work, FLOW_ARGS); break;
         }
-#undef DEP_ARGS
+#undef FLOW_ARGS
         if (c->prof) c->prof->end(c->work, FWD ? PK_FWD : PK_BWD);
         HIP_CHECK(hipGetLastError());
         return ICCG_OK;
@@ -676,13 +776,44 @@ int launch_sweep_t(iccg_ctx *c, const void *in, void *out, const CgArgs &cg) {
     return ICCG_OK;
 }
 
-// fails loudly if a dependency wait of the single-launch sweep timed out
+// A failed single-launch sweep (error word set by a wavefront) is reported
+// and the word is cleared, so the context stays usable (for instance with
+// per-color launches).
+int report_sweep_err(iccg_ctx *c, int err) {
+    if (!err) return ICCG_OK;
+    (void)hipMemsetAsync(c->sweep_err.p, 0, sizeof(int), c->work);
+    (void)hipStreamSynchronize(c->work);
+    if (err == 2)
+        return set_error(ICCG_EHIP, "single-launch sweep: a producer task ran on another XCD than "
+                                    "its region (round-robin placement failed); use per-color launches");
+    return set_error(ICCG_EHIP, "single-launch sweep: a dependency wait exceeded its spin limit");
+}
+
+// fails loudly if a dependency wait of the single-launch sweep failed
 int check_sweep_err(iccg_ctx *c) {
     if (c->opt.sweep_launch != 1) return ICCG_OK;
     int err = 0;
     HIP_CHECK(hipMemcpyAsync(&err, c->sweep_err.p, sizeof(int), hipMemcpyDeviceToHost, c->work));
     HIP_CHECK(hipStreamSynchronize(c->work));
-    if (err) return set_error(ICCG_EHIP, "a sweep dependency wait exceeded its spin limit");
+    return report_sweep_err(c, err);
+}
+
+// The flag words hold (epoch << 4 | XCC id), so the epoch must stay below
+// 2^27: before it could get there, flags and epochs are cleared (host path,
+// never inside a captured graph).  `sweeps` bounds the launches to come.
+int flow_guard(iccg_ctx *c, long long sweeps) {
+    if (c->opt.sweep_launch != 1) return ICCG_OK;
+    if (c->flow_sweeps + sweeps < (1LL << 26)) {
+        c->flow_sweeps += sweeps;
+        return ICCG_OK;
+    }
+    for (DevSweep *d : {&c->fwd, &c->bwd}) {
+        const size_t nf = sizeof(int) * static_cast<size_t>(std::max(d->ntasks, 1));
+        HIP_CHECK(hipMemsetAsync(d->flag_loc.p, 0, nf, c->work));
+        HIP_CHECK(hipMemsetAsync(d->flag_rem.p, 0, nf, c->work));
+        HIP_CHECK(hipMemsetAsync(d->epoch.p, 0, sizeof(int), c->work));
+    }
+    c->flow_sweeps = sweeps;
     return ICCG_OK;
 }
 
@@ -809,10 +940,14 @@ int upload_sweep(iccg_ctx *c, const SweepPlan &plan, DevSweep &d) {
     d.ndeps = static_cast<long long>(plan.deps.size());
     ICCG_CHECK(d.deps.upload(plan.deps.data(), plan.deps.size(), c->work));
     ICCG_CHECK(d.wg_task.upload(plan.wg_task.data(), plan.wg_task.size(), c->work));
-    ICCG_CHECK(d.flags.alloc(std::max(d.ntasks, 1)));
+    ICCG_CHECK(d.flag_loc.alloc(std::max(d.ntasks, 1)));
+    ICCG_CHECK(d.flag_rem.alloc(std::max(d.ntasks, 1)));
     ICCG_CHECK(d.epoch.alloc(1));
-    HIP_CHECK(hipMemsetAsync(d.flags.p, 0, sizeof(int) * std::max(d.ntasks, 1), c->work));
+    HIP_CHECK(hipMemsetAsync(d.flag_loc.p, 0, sizeof(int) * std::max(d.ntasks, 1), c->work));
+    HIP_CHECK(hipMemsetAsync(d.flag_rem.p, 0, sizeof(int) * std::max(d.ntasks, 1), c->work));
     HIP_CHECK(hipMemsetAsync(d.epoch.p, 0, sizeof(int), c->work));
+    d.remote_tasks = plan.remote_tasks;
+    d.exported_rows = plan.exported_rows;
     ICCG_CHECK(d.chunks.upload(plan.chunks.data(), plan.chunks.size(), c->work));
     ICCG_CHECK(d.meta.upload(plan.meta.data(), plan.meta.size(), c->work));
     ICCG_CHECK(d.scol.upload(plan.slot_col.data(), plan.slot_col.size(), c->work));
@@ -955,8 +1090,7 @@ int read_scalars(iccg_ctx *c) {
     HIP_CHECK(hipMemcpyAsync(c->h_scal, c->scal.p, sizeof(DevScalars), hipMemcpyDeviceToHost, c->work));
     HIP_CHECK(hipMemcpyAsync(&c->h_err, c->sweep_err.p, sizeof(int), hipMemcpyDeviceToHost, c->work));
     HIP_CHECK(hipStreamSynchronize(c->work));
-    if (c->h_err) return set_error(ICCG_EHIP, "a sweep dependency wait exceeded its spin limit");
-    return ICCG_OK;
+    return report_sweep_err(c, c->h_err);
 }
 
 // partial sums of (a, b) into part, then the fixed-order total
@@ -971,6 +1105,7 @@ int solve_impl(iccg_ctx *c, const double *b, double *x, double tol, int maxit, i
     if (!b || !x) return set_error(ICCG_EINVAL, "null b or x");
     if (!(tol >= 0.0) || maxit < 0) return set_error(ICCG_EINVAL, "need tol >= 0 and maxit >= 0");
     if (!c->has_factor) return set_error(ICCG_ESTATE, "no factor: call ic0_factor or iccg_set_factor first");
+    ICCG_CHECK(flow_guard(c, 2LL * maxit + 64));
     const int n = c->n;
     hipStream_t s = c->work;
     const int hist_cap = maxit + 1;
@@ -1100,6 +1235,10 @@ int iccg_setup(iccg_ctx **out, int n, const int *rowptr, const int *col, const d
         if (c->opt.pack_rows < 1 || c->opt.pack_rows > kChunkRows) c->opt.pack_rows = kChunkRows;
         if (c->opt.sweep_launch != 0 && c->opt.sweep_launch != 1)
             return set_error(ICCG_EINVAL, "sweep_launch must be 0 or 1");
+        // the single-launch sweep addresses vectors and flags through 32-bit
+        // buffer ranges
+        if (c->opt.sweep_launch == 1 && n >= (1 << 27))
+            return set_error(ICCG_EINVAL, "the single-launch sweep needs n < 2^27");
         HostSetup hs;
         ICCG_CHECK(validate(n, rowptr, col, val, nblocks, block_ptr, ncolors, color_ptr,
                             c->opt.pack_rows, hs));
@@ -1193,6 +1332,7 @@ int ic_apply(iccg_ctx *c, const double *r, double *z) {
         if (!r || !z) return set_error(ICCG_EINVAL, "null vector");
         if (r == z) return set_error(ICCG_EINVAL, "r and z must not alias");
         if (!c->has_factor) return set_error(ICCG_ESTATE, "no factor");
+        ICCG_CHECK(flow_guard(c, 2));
         ICCG_CHECK((launch_sweep<true, SW_APPLY>(c, r, ytmp(c), no_cg())));
         ICCG_CHECK((launch_sweep<false, SW_APPLY>(c, ytmp(c), z, no_cg())));
         return check_sweep_err(c);
@@ -1203,6 +1343,7 @@ int ic_forward(iccg_ctx *c, const double *r, double *y) {
     return entry(c, [&]() -> int {
         if (!r || !y) return set_error(ICCG_EINVAL, "null vector");
         if (!c->has_factor) return set_error(ICCG_ESTATE, "no factor");
+        ICCG_CHECK(flow_guard(c, 1));
         if (c->fp32()) {
             ICCG_CHECK((launch_sweep<true, SW_APPLY>(c, r, c->y32.p, no_cg())));
             hipLaunchKernelGGL((k_convert<double, float>), dim3(c->vec_blocks), dim3(kVecThreads), 0,
@@ -1221,6 +1362,7 @@ int ic_backward(iccg_ctx *c, const double *y, double *z) {
         if (!y || !z) return set_error(ICCG_EINVAL, "null vector");
         if (y == z) return set_error(ICCG_EINVAL, "y and z must not alias");
         if (!c->has_factor) return set_error(ICCG_ESTATE, "no factor");
+        ICCG_CHECK(flow_guard(c, 1));
         if (c->fp32()) {
             hipLaunchKernelGGL((k_convert<float, double>), dim3(c->vec_blocks), dim3(kVecThreads), 0,
                                c->work, c->n, c->y32.p, y);

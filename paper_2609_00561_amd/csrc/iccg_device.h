@@ -91,10 +91,11 @@ struct DevSweep {
     DevArray<int> scol, ssrc;
     DevArray<double> sval64;
     DevArray<float> sval32;
-    // single-launch sweep: ticket counter, per-task epoch flags, dependency lists
+    // single-launch sweep: sweep number, per-task flags, dependency lists
     DevArray<int> epoch;            // sweep number, bumped before every launch
-    DevArray<int> flags, dep_ptr, deps, wg_task;
+    DevArray<int> flag_loc, flag_rem, dep_ptr, deps, wg_task;
     long long ndeps = 0;
+    long long remote_tasks = 0, exported_rows = 0;
 };
 
 // Per-launch HIP-event timing of an instrumented (eager) solve.
@@ -182,6 +183,7 @@ struct iccg_ctx {
     int spmv_blocks = 1, vec_blocks = 1;
     hipGraphExec_t graph = nullptr;
     int graph_iters = 0;
+    long long flow_sweeps = 0;    // single-launch sweeps since the flags were last cleared
     double last_ms = 0.0;
     int last_iters = 0;
     int last_hist = 0;

@@ -32,20 +32,31 @@ struct Chunk {
 static_assert(sizeof(Chunk) == 16, "Chunk layout");
 
 // One wavefront task: its first chunk in processing order (forward: lowest,
-// backward: highest) inline, so a task starts from a single 32-byte load, and
-// the range [c0, c1) of all its chunks.
+// backward: highest) inline, so a task starts from a single 32-byte load, the
+// range [c0, c1) of all its chunks and, for the single-launch sweep, its
+// dependency list deps[dep0, dep0 + ndeps) and kind bits.
 struct TaskRec {
     Chunk first;
     int32_t c0, c1;
-    int32_t nchunks;
-    int32_t pad;
+    int32_t dep0;
+    int32_t kind_ndeps;   // kTaskRemote | kTaskExports | ndeps << 2
+    int nchunks() const { return c1 - c0; }
 };
 static_assert(sizeof(TaskRec) == 32, "TaskRec layout");
 
 // Per-row schedule word: number of entries whose value is final before the
-// chunk starts (bits 0..15), number of entries inside the chunk (bits
-// 16..23), intra-chunk level (bits 24..31).  The row's entries are stored
-// "before-chunk first", each group in ascending column order.
+// chunk starts (bits 0..14), the export bit (bit 15, see kMetaExport),
+// number of entries inside the chunk (bits 16..23), intra-chunk level (bits
+// 24..31).  The row's entries are stored "before-chunk first", each group in
+// ascending column order.
+constexpr uint32_t kMetaNextMask = 0x7fffu;
+// Single-launch sweep: the row is read by a task of another region (or by a
+// task that reads through device-coherent loads), so its value is also
+// written through to memory.
+constexpr uint32_t kMetaExport = 0x8000u;
+// TaskRec.kind bits of the single-launch sweep.
+constexpr int kTaskRemote = 1;   // some dependency is in another region
+constexpr int kTaskExports = 2;  // some row of the task has kMetaExport
 inline uint32_t pack_meta(int n_ext, int n_int, int level) {
     return static_cast<uint32_t>(n_ext) | (static_cast<uint32_t>(n_int) << 16) |
            (static_cast<uint32_t>(level) << 24);
@@ -72,8 +83,10 @@ struct SweepPlan {
     // launch table of the single-launch sweep: workgroup b runs task wg_task[b].
     // Workgroups follow the processing order color by color; inside a color,
     // the workgroups dealt to one XCD (b mod 8) get one contiguous region of
-    // the color's tasks.
+    // the color's tasks, the same region of the domain in every color.
     std::vector<int> wg_task;
+    long long remote_tasks = 0;        // tasks with kTaskRemote
+    long long exported_rows = 0;       // rows with kMetaExport
 };
 
 // Sliced ELL copy of A' for the SpMV: slices of 64 consecutive rows; entry k

@@ -88,7 +88,7 @@ int build_sweep_plan(bool forward, int n, const int *rowptr, const int *col, con
                 }
             }
             level[t] = lev;
-            if (re.ext.size() > 0xffff) return set_error(ICCG_EINVAL, "a row has more than 65535 off-diagonal entries in one triangle");
+            if (re.ext.size() > kMetaNextMask) return set_error(ICCG_EINVAL, "a row has more than 32767 off-diagonal entries in one triangle");
             width = std::max(width, static_cast<int>(re.ext.size() + re.inn.size()));
             depth = std::max(depth, lev + 1);
             out.meta[i] = pack_meta(static_cast<int>(re.ext.size()), static_cast<int>(re.inn.size()), lev);
@@ -161,13 +161,44 @@ int build_sweep_plan(bool forward, int n, const int *rowptr, const int *col, con
         for (int b = B; b < B + T; ++b) out.wg_task[b] = next[b & 7]++;
         B += T;
     }
+    // Regions of the single-launch sweep (the XCD slot each task is dealt to).
+    // Values pass between tasks of one region through that XCD's L2.  A task
+    // with a dependency in another region reads all of its before-chunk values
+    // with device-coherent loads, so every row such a task reads (its own
+    // earlier chunks included) is written through to memory: the export bit.
+    std::vector<int> region(ntasks, 0);
+    for (int b = 0; b < ntasks; ++b) region[out.wg_task[b]] = b & 7;
+    std::vector<int> kind(ntasks, 0);
+    for (int t = 0; t < ntasks; ++t)
+        for (int d = out.dep_ptr[t]; d < out.dep_ptr[t + 1]; ++d)
+            if (region[out.deps[d]] != region[t]) kind[t] |= kTaskRemote;
+    for (int t = 0; t < ntasks; ++t) {
+        if (!(kind[t] & kTaskRemote)) continue;
+        ++out.remote_tasks;
+        for (int ch = out.task_chunk_ptr[t]; ch < out.task_chunk_ptr[t + 1]; ++ch) {
+            const int r0 = chunk_rows[ch].first, r1 = chunk_rows[ch].second;
+            for (int i = r0; i < r1; ++i)
+                for (int k = rowptr[i]; k < rowptr[i + 1]; ++k) {
+                    const int j = col[k];
+                    if (forward ? (j >= i) : (j <= i)) continue;
+                    if (j >= r0 && j < r1) continue;
+                    if (!(out.meta[j] & kMetaExport)) {
+                        out.meta[j] |= kMetaExport;
+                        ++out.exported_rows;
+                        kind[task_of_row[j]] |= kTaskExports;
+                    }
+                }
+        }
+    }
     out.tasks.resize(ntasks);
     for (int t = 0; t < ntasks; ++t) {
         TaskRec &tr = out.tasks[t];
         tr.c0 = out.task_chunk_ptr[t];
         tr.c1 = out.task_chunk_ptr[t + 1];
-        tr.nchunks = tr.c1 - tr.c0;
-        tr.pad = 0;
+        const int nd = out.dep_ptr[t + 1] - out.dep_ptr[t];
+        if (nd >= (1 << 29)) return set_error(ICCG_EINVAL, "a task has too many dependencies");
+        tr.dep0 = out.dep_ptr[t];
+        tr.kind_ndeps = kind[t] | (nd << 2);
         tr.first = out.chunks[forward ? tr.c0 : tr.c1 - 1];
     }
     return ICCG_OK;

@@ -339,16 +339,20 @@ def test_fp32_solve_converges(case):
     assert res["iters"] <= ref.iters * 1.2 + 5
 
 
-@pytest.mark.parametrize("case", [CASES[1], CASES[3], CASES[6], CASES[7]], ids=_ids)
-def test_single_launch_sweep_identical_to_per_color(case):
-    """The single-launch sweep (per-task dependency waits) computes the same
-    per-row terms as one launch per color: outputs and solves are bit-identical."""
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("case", [CASES[1], CASES[3], CASES[6], CASES[7], CASES[8],
+                                  ("poisson7_64", "abmc", 16)], ids=_ids)
+def test_single_launch_sweep_identical_to_per_color(case, precision):
+    """The single-launch sweep (per-task dependency waits, values passed
+    through the XCD's L2 inside a region and written through across regions)
+    computes the same per-row terms as one launch per color: outputs and
+    solves are bit-identical."""
     cs = _case(*case)
     Ap = cs[4]
     r = np.random.default_rng(8).standard_normal(Ap.n)
     outs, sols = [], []
     for mode in ("per_color", "single"):
-        with _ctx(cs, sweep_launch=mode) as ctx:
+        with _ctx(cs, sweep_launch=mode, precision=precision) as ctx:
             zd = torch.zeros(Ap.n, dtype=torch.float64, device="cuda")
             for _ in range(3):                      # repeated launches reuse the epoch flags
                 ctx.ic_apply(_dev(r), zd)
