@@ -67,12 +67,17 @@ typedef struct {
     int   pack_rows;    /* max rows one wavefront task packs from consecutive small
                            blocks of one color (1..64, default 64)                */
     int   use_graph;    /* 1 = replay the iteration batch as a captured HIP graph  */
-    int   sweep_launch; /* 0 = one kernel launch per color (default); 1 = one launch
-                           per sweep, each wavefront task waiting only for the
-                           earlier-color tasks it reads (same arithmetic)         */
+    int   sweep_launch; /* 0 = one kernel launch per color (default); 1 = one
+                           persistent launch per sweep, each wavefront task waiting
+                           only for the earlier-color tasks it reads (same
+                           arithmetic, bit-identical results)                     */
+    int   sweep_grid;   /* single-launch sweep: its workgroups, all of which must
+                           be resident at once (0 = 8 per compute unit; otherwise
+                           this many, bounded by the resident capacity and rounded
+                           down to a multiple of 8, at least 8)                  */
 } iccg_options;
 
-/* Fills *opt with the defaults above (FP64, null stream, 32, 64, 1, 0). */
+/* Fills *opt with the defaults above (FP64, null stream, 32, 64, 1, 0, 0). */
 void iccg_default_options(iccg_options *opt);
 
 /* ------------------------------------------------------------------------ */
@@ -214,6 +219,11 @@ typedef struct {
     double spmv_bytes;              /* algorithmic bytes of one SpMV              */
     double last_solve_ms;           /* device time of the last iccg_solve         */
     int    last_iters;
+    int    sweep_resident;          /* single-launch sweep: workgroups of the last
+                                       launch (0 before the first)                */
+    long long remote_tasks;         /* single-launch sweep (forward schedule):
+                                       tasks with a dependency in another region  */
+    long long exported_rows;        /* rows written through for other regions     */
 } iccg_info;
 
 int iccg_get_info(iccg_ctx *c, iccg_info *info);

@@ -608,6 +608,11 @@ struct FlowWait {
     }
 };
 
+// Persistent form: the grid holds R resident workgroups (R a multiple of 8,
+// or R = ntasks) and workgroup g runs the table positions g, g + R, g + 2R, ...
+// in order, all in one region.  Dependencies always sit at smaller positions,
+// so the smallest unfinished position is always being worked on: with every
+// workgroup resident, the sweep completes.
 template <typename F, bool FWD, int KMAX, int MODE, typename TIn, typename TOut>
 __global__ __launch_bounds__(64) void k_sweep_flow(const TaskRec *__restrict__ tasks,
                                                    const Chunk *__restrict__ chunks,
@@ -620,51 +625,54 @@ __global__ __launch_bounds__(64) void k_sweep_flow(const TaskRec *__restrict__ t
     if (cg.sc && cg.sc->done != DONE_RUNNING) return;
     __shared__ F ys[kChunkRows];
     const int epoch = *fa.epoch;
-    const int task = fa.wg_task[blockIdx.x];
     const int xcc = xcc_id();
-    const TaskRec tr = tasks[task];
-    const int kind = tr.kind_ndeps & 3, nchunks = tr.c1 - tr.c0;
-    const bool remote = (kind & kTaskRemote) != 0;
     const double alpha = (MODE == SW_CG_FWD) ? cg.sc->alpha : 0.0;
-    double dacc = 0.0;
-    const __amdgpu_buffer_rsrc_t rs_out = make_rsrc(out, static_cast<long long>(n) * sizeof(TOut));
-    const FlowWait wait{&fa, make_rsrc(fa.flag_loc, 4LL * fa.ntasks), task, epoch, xcc,
-                        tr.dep0, tr.kind_ndeps >> 2, remote};
-    F yv;
-    uint32_t m;
-    sweep_chunk<F, FWD, KMAX, MODE, TIn, TOut>(tr.first, meta, scol, sval, inv, in, out, cg, alpha,
-                                               ys, dacc, wait, FlowMem{rs_out, remote, nchunks == 1},
-                                               yv, m);
-    for (int q = 1; q < nchunks; ++q) {
-        __builtin_amdgcn_s_waitcnt(0);   // this chunk's stores are complete before they are read
-        __syncthreads();
-        const Chunk ch = chunks[FWD ? tr.c0 + q : tr.c1 - 1 - q];
-        sweep_chunk<F, FWD, KMAX, MODE, TIn, TOut>(ch, meta, scol, sval, inv, in, out, cg, alpha,
-                                                   ys, dacc, NoWait(),
-                                                   FlowMem{rs_out, remote, q == nchunks - 1}, yv, m);
-    }
-    if (MODE != SW_APPLY) {
-        const double tsum = wave_sum(dacc);
-        if (threadIdx.x == 0) cg.part[task] = tsum;
-    }
     const int word = (epoch << 4) | xcc;
-    // signal the region: every store of this wavefront has reached L2
-    __builtin_amdgcn_s_waitcnt(0);
-    __atomic_signal_fence(__ATOMIC_SEQ_CST);
-    if (threadIdx.x == 0)
-        __hip_atomic_store(fa.flag_loc + task, word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-    if (kind & kTaskExports) {
-        // then write the last chunk's exported rows through and signal the
-        // other regions
-        const int nr = (FWD ? chunks[tr.c1 - 1] : chunks[tr.c0]).shape & 0xffff;
-        const int row0 = (FWD ? chunks[tr.c1 - 1] : chunks[tr.c0]).row0;
-        if (static_cast<int>(threadIdx.x) < nr && (m & kMetaExport))
-            __hip_atomic_store(out + row0 + threadIdx.x, static_cast<TOut>(yv), __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
+    const __amdgpu_buffer_rsrc_t rs_out = make_rsrc(out, static_cast<long long>(n) * sizeof(TOut));
+    const __amdgpu_buffer_rsrc_t rs_loc = make_rsrc(fa.flag_loc, 4LL * fa.ntasks);
+    for (int pos = blockIdx.x; pos < fa.ntasks; pos += gridDim.x) {
+        const int task = fa.wg_task[pos];
+        const TaskRec tr = tasks[task];
+        const int kind = tr.kind_ndeps & 3, nchunks = tr.c1 - tr.c0;
+        const bool remote = (kind & kTaskRemote) != 0;
+        double dacc = 0.0;
+        const FlowWait wait{&fa, rs_loc, task, epoch, xcc, tr.dep0, tr.kind_ndeps >> 2, remote};
+        F yv;
+        uint32_t m;
+        sweep_chunk<F, FWD, KMAX, MODE, TIn, TOut>(tr.first, meta, scol, sval, inv, in, out, cg,
+                                                   alpha, ys, dacc, wait,
+                                                   FlowMem{rs_out, remote, nchunks == 1}, yv, m);
+        for (int q = 1; q < nchunks; ++q) {
+            __builtin_amdgcn_s_waitcnt(0);   // this chunk's stores are complete before they are read
+            __syncthreads();
+            const Chunk ch = chunks[FWD ? tr.c0 + q : tr.c1 - 1 - q];
+            sweep_chunk<F, FWD, KMAX, MODE, TIn, TOut>(ch, meta, scol, sval, inv, in, out, cg, alpha,
+                                                       ys, dacc, NoWait(),
+                                                       FlowMem{rs_out, remote, q == nchunks - 1}, yv, m);
+        }
+        if (MODE != SW_APPLY) {
+            const double tsum = wave_sum(dacc);
+            if (threadIdx.x == 0) cg.part[task] = tsum;
+        }
+        // signal the region: every store of this wavefront has reached L2
         __builtin_amdgcn_s_waitcnt(0);
         __atomic_signal_fence(__ATOMIC_SEQ_CST);
         if (threadIdx.x == 0)
-            __hip_atomic_store(fa.flag_rem + task, word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(fa.flag_loc + task, word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (kind & kTaskExports) {
+            // then write the last chunk's exported rows through and signal the
+            // other regions
+            const Chunk last = nchunks == 1 ? tr.first : chunks[FWD ? tr.c1 - 1 : tr.c0];
+            const int nr = last.shape & 0xffff;
+            if (static_cast<int>(threadIdx.x) < nr && (m & kMetaExport))
+                __hip_atomic_store(out + last.row0 + threadIdx.x, static_cast<TOut>(yv),
+                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __builtin_amdgcn_s_waitcnt(0);
+            __atomic_signal_fence(__ATOMIC_SEQ_CST);
+            if (threadIdx.x == 0)
+                __hip_atomic_store(fa.flag_rem + task, word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        __syncthreads();
     }
 }
 
@@ -717,6 +725,37 @@ SweepArgs<F> sweep_args(const iccg_ctx *c, const DevSweep &s) {
     return a;
 }
 
+// Workgroups of a persistent single-launch sweep.  Every workgroup must be
+// resident at once, so the count is bounded by the occupancy the kernel's own
+// register and LDS use allow (the runtime's occupancy query can report more
+// 64-thread workgroups per CU than fit), and by default by 8 per CU, the
+// fastest measured setting.  A multiple of 8, so a workgroup's table
+// positions all fall in one region; at most one per task.  Cached per kernel.
+int resident_grid(iccg_ctx *c, const void *kfn, int ntasks, int *grid) {
+    auto it = c->resident.find(kfn);
+    int per_cu = 0;
+    if (it != c->resident.end()) {
+        per_cu = it->second;
+    } else {
+        HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kfn, 64, 0));
+        hipFuncAttributes fa;
+        HIP_CHECK(hipFuncGetAttributes(&fa, kfn));
+        // one wave per workgroup: 4 SIMDs x min(8, 512 / VGPRs rounded up to 8)
+        const int vgprs = std::max(8, (fa.numRegs + 7) / 8 * 8);
+        per_cu = std::min(per_cu, 4 * std::min(8, 512 / vgprs));
+        if (fa.sharedSizeBytes > 0)
+            per_cu = std::min<int>(per_cu, static_cast<int>((160 * 1024) / fa.sharedSizeBytes));
+        c->resident[kfn] = per_cu;
+    }
+    long long r = static_cast<long long>(std::min(per_cu, 8)) * c->num_cu;
+    if (c->opt.sweep_grid > 0)
+        r = std::min<long long>(static_cast<long long>(per_cu) * c->num_cu, std::max(c->opt.sweep_grid, 8));
+    r -= r % 8;
+    if (r < 8) return set_error(ICCG_EHIP, "single-launch sweep: no resident capacity for its kernel");
+    *grid = static_cast<int>(std::min<long long>(r, std::max(ntasks, 1)));
+    return ICCG_OK;
+}
+
 // All colors of one sweep direction: one launch per color (colors ascending
 // for the forward sweep, descending for the backward sweep), or one launch for
 // all of them with per-task dependency waits.
@@ -741,7 +780,17 @@ int launch_sweep_t(iccg_ctx *c, const void *in, void *out, const CgArgs &cg) {
         fa.err = c->sweep_err.p;
         hipLaunchKernelGGL(k_bump_epoch, dim3(1), dim3(64), 0, c->work, d.epoch.p, cg.sc);
         if (c->prof) c->prof->begin(c->work);
-        const dim3 grid(d.ntasks), block(64);
+        const void *kfn = nullptr;
+        switch (d.kmax) {
+            case 4: kfn = reinterpret_cast<const void *>(&k_sweep_flow<F, FWD, 4, MODE, TIn, TOut>); break;
+            case 8: kfn = reinterpret_cast<const void *>(&k_sweep_flow<F, FWD, 8, MODE, TIn, TOut>); break;
+            case 16: kfn = reinterpret_cast<const void *>(&k_sweep_flow<F, FWD, 16, MODE, TIn, TOut>); break;
+            default: kfn = reinterpret_cast<const void *>(&k_sweep_flow<F, FWD, 32, MODE, TIn, TOut>); break;
+        }
+        int R = 0;
+        ICCG_CHECK(resident_grid(c, kfn, d.ntasks, &R));
+        c->last_resident = R;
+        const dim3 grid(R), block(64);
 #define FLOW_ARGS a.tasks, a.chunks, a.meta, a.scol, a.sval, a.inv, fa, c->n, pin, pout, cg
         switch (d.kmax) {
             case 4: hipLaunchKernelGGL((k_sweep_flow<F, FWD, 4, MODE, TIn, TOut>), grid, block, 0, c->work, FLOW_ARGS); break;
@@ -1200,6 +1249,7 @@ void iccg_default_options(iccg_options *opt) {
     opt->pack_rows = 64;
     opt->use_graph = 1;
     opt->sweep_launch = 0;
+    opt->sweep_grid = 0;
 }
 
 const char *iccg_strerror(int st) {
@@ -1235,6 +1285,7 @@ int iccg_setup(iccg_ctx **out, int n, const int *rowptr, const int *col, const d
         if (c->opt.pack_rows < 1 || c->opt.pack_rows > kChunkRows) c->opt.pack_rows = kChunkRows;
         if (c->opt.sweep_launch != 0 && c->opt.sweep_launch != 1)
             return set_error(ICCG_EINVAL, "sweep_launch must be 0 or 1");
+        if (c->opt.sweep_grid < 0) return set_error(ICCG_EINVAL, "sweep_grid must be >= 0");
         // the single-launch sweep addresses vectors and flags through 32-bit
         // buffer ranges
         if (c->opt.sweep_launch == 1 && n >= (1 << 27))
@@ -1244,6 +1295,9 @@ int iccg_setup(iccg_ctx **out, int n, const int *rowptr, const int *col, const d
                             c->opt.pack_rows, hs));
         c->user = static_cast<hipStream_t>(c->opt.stream);
         HIP_CHECK(hipStreamCreateWithFlags(&c->work, hipStreamNonBlocking));
+        int dev = 0;
+        HIP_CHECK(hipGetDevice(&dev));
+        HIP_CHECK(hipDeviceGetAttribute(&c->num_cu, hipDeviceAttributeMultiprocessorCount, dev));
         HIP_CHECK(hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming));
         HIP_CHECK(hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming));
         HIP_CHECK(hipEventCreate(&c->ev_t0));
@@ -1461,6 +1515,9 @@ int iccg_get_info(iccg_ctx *c, iccg_info *info) {
     info->spmv_bytes = 12.0 * c->nnz + 20.0 * c->n + 4.0;
     info->last_solve_ms = c->last_ms;
     info->last_iters = c->last_iters;
+    info->sweep_resident = c->last_resident;
+    info->remote_tasks = c->fwd.remote_tasks;
+    info->exported_rows = c->fwd.exported_rows;
     return ICCG_OK;
 }
 

@@ -8,6 +8,7 @@
 
 #include <cstring>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 using namespace iccg;
@@ -184,6 +185,9 @@ struct iccg_ctx {
     hipGraphExec_t graph = nullptr;
     int graph_iters = 0;
     long long flow_sweeps = 0;    // single-launch sweeps since the flags were last cleared
+    int num_cu = 0;                 // compute units of the device
+    int last_resident = 0;          // workgroups of the last single-launch sweep
+    std::unordered_map<const void *, int> resident;   // resident workgroups per CU, per kernel
     double last_ms = 0.0;
     int last_iters = 0;
     int last_hist = 0;

@@ -55,7 +55,8 @@ class IccgError(RuntimeError):
 class _Options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("stream", ctypes.c_void_p),
                 ("check_every", ctypes.c_int), ("pack_rows", ctypes.c_int),
-                ("use_graph", ctypes.c_int), ("sweep_launch", ctypes.c_int)]
+                ("use_graph", ctypes.c_int), ("sweep_launch", ctypes.c_int),
+                ("sweep_grid", ctypes.c_int)]
 
 
 class _Info(ctypes.Structure):
@@ -65,7 +66,9 @@ class _Info(ctypes.Structure):
                 ("max_block", ctypes.c_int), ("max_depth", ctypes.c_int),
                 ("precision", ctypes.c_int), ("has_factor", ctypes.c_int),
                 ("sweep_bytes", ctypes.c_double), ("spmv_bytes", ctypes.c_double),
-                ("last_solve_ms", ctypes.c_double), ("last_iters", ctypes.c_int)]
+                ("last_solve_ms", ctypes.c_double), ("last_iters", ctypes.c_int),
+                ("sweep_resident", ctypes.c_int), ("remote_tasks", ctypes.c_longlong),
+                ("exported_rows", ctypes.c_longlong)]
 
 
 _lib = None
@@ -209,7 +212,7 @@ class Context:
 
     def __init__(self, rowptr, col, val, block_ptr, color_ptr, precision: str = "fp64",
                  stream=None, check_every: int = 32, pack_rows: int = 64, use_graph: bool = True,
-                 sweep_launch: str = "per_color"):
+                 sweep_launch: str = "per_color", sweep_grid: int = 0):
         import torch
         lib = load()
         opt = _Options()
@@ -222,6 +225,7 @@ class Context:
         opt.pack_rows = int(pack_rows)
         opt.use_graph = 1 if use_graph else 0
         opt.sweep_launch = {"per_color": 0, "single": 1}[sweep_launch]
+        opt.sweep_grid = int(sweep_grid)
         self._keep = [_host_i32(rowptr), _host_i32(col), _host_f64(val), _host_i32(block_ptr),
                       _host_i32(color_ptr)]
         rp, cl, vl, bp, cp = self._keep

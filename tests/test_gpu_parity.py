@@ -346,13 +346,14 @@ def test_single_launch_sweep_identical_to_per_color(case, precision):
     """The single-launch sweep (per-task dependency waits, values passed
     through the XCD's L2 inside a region and written through across regions)
     computes the same per-row terms as one launch per color: outputs and
-    solves are bit-identical."""
+    solves are bit-identical.  Small persistent grids (8 and 64 workgroups)
+    make every workgroup run many tasks in sequence."""
     cs = _case(*case)
     Ap = cs[4]
     r = np.random.default_rng(8).standard_normal(Ap.n)
     outs, sols = [], []
-    for mode in ("per_color", "single"):
-        with _ctx(cs, sweep_launch=mode, precision=precision) as ctx:
+    for mode, grid in (("per_color", 0), ("single", 0), ("single", 8), ("single", 64)):
+        with _ctx(cs, sweep_launch=mode, sweep_grid=grid, precision=precision) as ctx:
             zd = torch.zeros(Ap.n, dtype=torch.float64, device="cuda")
             for _ in range(3):                      # repeated launches reuse the epoch flags
                 ctx.ic_apply(_dev(r), zd)
@@ -360,5 +361,6 @@ def test_single_launch_sweep_identical_to_per_color(case, precision):
             xd = torch.zeros(Ap.n, dtype=torch.float64, device="cuda")
             res = ctx.solve(_dev(cs[6]), xd)
             sols.append((res["iters"], _host(xd)))
-    assert np.array_equal(outs[0], outs[1])
-    assert sols[0][0] == sols[1][0] and np.array_equal(sols[0][1], sols[1][1])
+    for k in range(1, len(outs)):
+        assert np.array_equal(outs[0], outs[k]), k
+        assert sols[0][0] == sols[k][0] and np.array_equal(sols[0][1], sols[k][1]), k
