@@ -282,10 +282,10 @@ def main():
     prof = ctx.profile_solve(torch.tensor(bp, device=dev),
                              torch.zeros(A.n, dtype=torch.float64, device=dev), tol=args.tol)
     # algorithmic bytes per sweep: the substitution's compulsory bytes (library
-    # info) plus the fused CG work: the forward sweep also reads x, p, q and
-    # writes x, r (40 B/row); the backward sweep also reads r for (r, z)
+    # info) plus the fused CG work: the forward sweep also reads q and writes r
+    # (16 B/row); the backward sweep also reads r for (r, z)
     sweep_bytes = info["sweep_bytes"]
-    fwd_bytes = sweep_bytes + 40.0 * A.n
+    fwd_bytes = sweep_bytes + 16.0 * A.n
     bwd_bytes = sweep_bytes + 8.0 * A.n
     fwd_launch_ms = prof["fwd_ms"] / max(prof["fwd_launches"], 1)
     bwd_launch_ms = prof["bwd_ms"] / max(prof["bwd_launches"], 1)

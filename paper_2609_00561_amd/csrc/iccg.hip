@@ -1,14 +1,16 @@
 // MI355X (gfx950) device path of block-multicolored ICCG and the C ABI in
 // include/iccg.h.
 //
-// Per CG iteration (Section 5, IC(0)-preconditioned CG):
+// Per CG iteration k (Section 5, IC(0)-preconditioned CG):
+//   x += alpha_{k-1} p_{k-1}, p = z + beta p  k_update_p (the x update of the
+//                                             previous iteration, deferred)
 //   q = A'p with (p, q)                       k_spmv
 //   alpha = (r, z)/(p, q)                     k_reduce
-//   x += alpha p, r -= alpha q, ||r||^2       k_update_xr, k_reduce (stopping test)
+//   r -= alpha q, ||r||^2 per task,
 //   y = L^{-1} r   (Algorithm 1)              k_sweep<forward>, one launch per color
 //   z = L^{-T} y, (r, z) per task             k_sweep<backward>, one launch per color
-//   beta, rho                                 k_reduce
-//   p = z + beta p                            k_update_p
+//   stopping test on ||r||, beta, rho         k_reduce_rr_beta
+// and after the last iteration x += alpha p   k_axpy_alpha
 // The sweeps give every 64-row chunk of a color one wavefront (one lane per
 // row): the terms whose values were final before the chunk started are
 // gathered by all lanes at once, the in-chunk terms follow the chunk's level
@@ -94,14 +96,34 @@ __device__ inline double block_sum(double v) {
     return s;
 }
 
+// Thread t's share of a fixed-order sum over part[0, np): pairs (2i, 2i+1)
+// for i = t, t + NT, ... in that order, loaded 16 bytes at a time with up to
+// 16 pairs in flight, so one workgroup covers 32K partials in one round trip.
+template <int NT>
+__device__ __forceinline__ double thread_partial(const double *__restrict__ part, int np) {
+    const int npair = np >> 1;
+    const double2 *p2 = reinterpret_cast<const double2 *>(part);
+    double v = 0.0;
+    for (int base = 0; base < npair; base += 16 * NT) {
+        double2 buf[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int i = base + u * NT + static_cast<int>(threadIdx.x);
+            buf[u] = i < npair ? p2[i] : make_double2(0.0, 0.0);
+        }
+#pragma unroll
+        for (int u = 0; u < 16; ++u) v += buf[u].x + buf[u].y;
+    }
+    if ((np & 1) && threadIdx.x == 0) v += part[np - 1];
+    return v;
+}
+
 __global__ __launch_bounds__(kReduceThreads) void k_reduce(const double *__restrict__ part,
                                                            int np, DevScalars *sc, int op,
                                                            double *__restrict__ out,
                                                            double *__restrict__ hist) {
     if (op != OP_STORE && op != OP_TRUE && op != OP_BNORM && sc->done != DONE_RUNNING) return;
-    double v = 0.0;
-#pragma unroll 8
-    for (int k = threadIdx.x; k < np; k += kReduceThreads) v += part[k];
+    double v = thread_partial<kReduceThreads>(part, np);
     v = block_sum<kReduceThreads>(v);
     if (threadIdx.x != 0) return;
     switch (op) {
@@ -142,6 +164,37 @@ __global__ __launch_bounds__(kReduceThreads) void k_reduce(const double *__restr
             break;
         case OP_TRUE: sc->relres_true = sqrt(v) / sc->bnorm; break;
     }
+}
+
+// End of a CG iteration in one launch: ||r||^2 from the forward sweep's
+// partials decides the stopping test (as OP_RR), then, if the iteration goes
+// on, (r, z) from the backward sweep's partials gives beta (as OP_BETA).  The
+// backward sweep does not depend on the stopping test, so it can run first;
+// after the last iteration its z is simply unused.  Same sums, same order as
+// two k_reduce launches.
+__global__ __launch_bounds__(kReduceThreads) void k_reduce_rr_beta(const double *__restrict__ rr_part,
+                                                                   int n_rr,
+                                                                   const double *__restrict__ rz_part,
+                                                                   int n_rz, DevScalars *sc,
+                                                                   double *__restrict__ hist) {
+    if (sc->done != DONE_RUNNING) return;
+    double a = thread_partial<kReduceThreads>(rr_part, n_rr);
+    double b = thread_partial<kReduceThreads>(rz_part, n_rz);
+    a = block_sum<kReduceThreads>(a);
+    __syncthreads();   // block_sum's scratch is reused
+    b = block_sum<kReduceThreads>(b);
+    if (threadIdx.x != 0) return;
+    const int it = sc->iter + 1;
+    sc->iter = it;
+    const double rel = sqrt(a) / sc->bnorm;
+    sc->relres = rel;
+    if (it < sc->hist_cap) hist[it] = rel;
+    if (rel <= sc->tol) { sc->done = DONE_CONVERGED; return; }
+    if (!isfinite(rel)) { sc->done = DONE_NAN; return; }
+    if (it >= sc->maxit) { sc->done = DONE_MAXIT; return; }
+    if (!isfinite(b)) { sc->done = DONE_NAN; return; }
+    sc->beta = b / sc->rho;
+    sc->rho = b;
 }
 
 __global__ void k_init_scalars(DevScalars *sc, double tol, int maxit, int hist_cap) {
@@ -244,15 +297,35 @@ __global__ __launch_bounds__(kVecThreads) void k_fill(int n, double *__restrict_
         dst[i] = v;
 }
 
-// p = z + beta p
-__global__ __launch_bounds__(kVecThreads) void k_update_p(int n, double *__restrict__ p,
+// x += alpha p (the previous iteration's step, alpha still in the scalar
+// block), then p = z + beta p.  alpha = beta = 0 and p = 0 before the first
+// iteration.
+__global__ __launch_bounds__(kVecThreads) void k_update_p(int n, double *__restrict__ x,
+                                                          double *__restrict__ p,
                                                           const double *__restrict__ z,
                                                           const DevScalars *sc) {
     if (sc->done != DONE_RUNNING) return;
-    const double beta = sc->beta;
+    const double alpha = sc->alpha, beta = sc->beta;
+    const int wg = xcd_remap(blockIdx.x, gridDim.x);
+    for (int i = wg * kVecThreads + threadIdx.x; i < n; i += gridDim.x * kVecThreads) {
+        const double pi = p[i];
+        x[i] = x[i] + alpha * pi;
+        p[i] = z[i] + beta * pi;
+    }
+}
+
+// x += alpha p once the iterations have stopped at the stopping test: the
+// last iteration's step, which no later k_update_p applies.  After a
+// breakdown (non-finite or non-positive (p, q), non-finite residual) x keeps
+// the last complete iterate.
+__global__ __launch_bounds__(kVecThreads) void k_axpy_alpha(int n, double *__restrict__ x,
+                                                            const double *__restrict__ p,
+                                                            const DevScalars *sc) {
+    if (sc->done != DONE_CONVERGED && sc->done != DONE_MAXIT) return;
+    const double alpha = sc->alpha;
     const int wg = xcd_remap(blockIdx.x, gridDim.x);
     for (int i = wg * kVecThreads + threadIdx.x; i < n; i += gridDim.x * kVecThreads)
-        p[i] = z[i] + beta * p[i];
+        x[i] = x[i] + alpha * p[i];
 }
 
 template <typename A, typename B>
@@ -324,15 +397,13 @@ struct SweepArgs {
 };
 
 // SW_APPLY: plain sweep.  SW_CG_FWD: forward sweep that first applies the CG
-// update of its own rows (x += alpha p, r -= alpha q) and substitutes the new
-// r, with part[task] = sum of r_i^2.  SW_DOT_BWD: backward sweep with
+// update of its own rows (r -= alpha q) and substitutes the new r, with
+// part[task] = sum of r_i^2.  SW_DOT_BWD: backward sweep with
 // part[task] = sum of rdot_i z_i.
 enum SweepMode : int { SW_APPLY = 0, SW_CG_FWD = 1, SW_DOT_BWD = 2 };
 
 struct CgArgs {
-    double *x;
     double *r;
-    const double *p;
     const double *q;
     const double *rdot;
     double *part;
@@ -434,9 +505,7 @@ __device__ __forceinline__ void sweep_chunk(const Chunk &ch, const uint32_t *__r
         m = meta[i];
         dinv = inv[i];
         if (MODE == SW_CG_FWD) {
-            const double pi = cg.p[i], qi = cg.q[i], xi = cg.x[i], r0 = cg.r[i];
-            const double ri = r0 - alpha * qi;
-            cg.x[i] = xi + alpha * pi;
+            const double ri = cg.r[i] - alpha * cg.q[i];
             cg.r[i] = ri;
             dacc += ri * ri;
             s = static_cast<F>(ri);
@@ -500,25 +569,38 @@ __global__ __launch_bounds__(64) void k_sweep(const TaskRec *__restrict__ tasks,
                                               const int *__restrict__ scol,
                                               const F *__restrict__ sval,
                                               const F *__restrict__ inv, int task_base,
-                                              int ntasks_color, const TIn *__restrict__ in,
+                                              int ntasks_color, ColorLayout lay,
+                                              const TIn *__restrict__ in,
                                               TOut *__restrict__ out, CgArgs cg) {
     if (cg.sc && cg.sc->done != DONE_RUNNING) return;
     __shared__ F ys[kChunkRows];
-    const int task = task_base + xcd_remap(blockIdx.x, ntasks_color);
-    const TaskRec tr = tasks[task];
+    const int local = xcd_remap(blockIdx.x, ntasks_color);
+    const int task = task_base + local;
     const double alpha = (MODE == SW_CG_FWD) ? cg.sc->alpha : 0.0;
     double dacc = 0.0;
     F yv;
     uint32_t m;
-    sweep_chunk<F, FWD, KMAX, MODE, TIn, TOut>(tr.first, meta, scol, sval, inv, in, out, cg, alpha,
-                                               ys, dacc, NoWait(), PlainMem(), yv, m);
-    const int nchunks = tr.c1 - tr.c0;
-    for (int q = 1; q < nchunks; ++q) {
-        // later chunks of this task read earlier chunks' results from memory
-        __syncthreads();
-        const Chunk ch = chunks[FWD ? tr.c0 + q : tr.c1 - 1 - q];
+    if (lay.uniform) {
+        // the chunk follows from the launch constants: no task record to wait for
+        Chunk ch;
+        ch.row0 = lay.row0 + kChunkRows * local;
+        ch.off = lay.off + kChunkRows * lay.width * local;
+        ch.shape = min(kChunkRows, lay.row0 + lay.rows - ch.row0) | (lay.width << 16);
+        ch.depth = lay.depth;
         sweep_chunk<F, FWD, KMAX, MODE, TIn, TOut>(ch, meta, scol, sval, inv, in, out, cg, alpha,
                                                    ys, dacc, NoWait(), PlainMem(), yv, m);
+    } else {
+        const TaskRec tr = tasks[task];
+        sweep_chunk<F, FWD, KMAX, MODE, TIn, TOut>(tr.first, meta, scol, sval, inv, in, out, cg,
+                                                   alpha, ys, dacc, NoWait(), PlainMem(), yv, m);
+        const int nchunks = tr.c1 - tr.c0;
+        for (int q = 1; q < nchunks; ++q) {
+            // later chunks of this task read earlier chunks' results from memory
+            __syncthreads();
+            const Chunk ch = chunks[FWD ? tr.c0 + q : tr.c1 - 1 - q];
+            sweep_chunk<F, FWD, KMAX, MODE, TIn, TOut>(ch, meta, scol, sval, inv, in, out, cg, alpha,
+                                                       ys, dacc, NoWait(), PlainMem(), yv, m);
+        }
     }
     if (MODE != SW_APPLY) {
         const double tsum = wave_sum(dacc);
@@ -803,7 +885,7 @@ int launch_sweep_t(iccg_ctx *c, const void *in, void *out, const CgArgs &cg) {
         HIP_CHECK(hipGetLastError());
         return ICCG_OK;
     }
-#define SWEEP_ARGS a.tasks, a.chunks, a.meta, a.scol, a.sval, a.inv, t0, t1 - t0, pin, pout, cg
+#define SWEEP_ARGS a.tasks, a.chunks, a.meta, a.scol, a.sval, a.inv, t0, t1 - t0, d.color_layout[col], pin, pout, cg
     if (c->prof) c->prof->begin(c->work);
     int launched = 0;
     for (int step = 0; step < c->ncolors; ++step) {
@@ -890,31 +972,32 @@ int launch_reduce(iccg_ctx *c, int np, int op, double *out) {
 // One CG iteration (all kernels return at once after the stopping test passed):
 //   1. p = z + beta p (beta = 0 and p = 0 before the first iteration)
 //   2. SpMV:     q = A p, alpha = rho / (p, q)
-//   3. forward:  x += alpha p, r -= alpha q, ||r|| stopping test, y = L^{-1} r
-//   4. backward: z = L^{-T} y, beta = (r, z)/rho, rho = (r, z)
+//   3. forward:  x += alpha p, r -= alpha q, ||r||^2 partials, y = L^{-1} r
+//   4. backward: z = L^{-T} y, (r, z) partials
+//   5. stopping test on ||r||, then beta = (r, z)/rho, rho = (r, z)
 int enqueue_iteration(iccg_ctx *c, long long j) {
     (void)j;
     DevScalars *sc = c->scal.p;
     double *p = c->p.p;
-    hipLaunchKernelGGL(k_update_p, dim3(c->vec_blocks), dim3(kVecThreads), 0, c->work, c->n, p, c->z.p, sc);
+    hipLaunchKernelGGL(k_update_p, dim3(c->vec_blocks), dim3(kVecThreads), 0, c->work, c->n, c->x.p, p,
+                       c->z.p, sc);
     HIP_CHECK(hipGetLastError());
     ICCG_CHECK(launch_spmv(c, SP_PLAIN, p, c->q.p, nullptr, sc));
     ICCG_CHECK(launch_reduce(c, c->spmv_blocks, OP_ALPHA, nullptr));
     CgArgs f = no_cg();
-    f.x = c->x.p;
     f.r = c->r.p;
-    f.p = p;
     f.q = c->q.p;
-    f.part = c->part.p;
+    f.part = c->part_rr.p;
     f.sc = sc;
     ICCG_CHECK((launch_sweep<true, SW_CG_FWD>(c, nullptr, ytmp(c), f)));
-    ICCG_CHECK(launch_reduce(c, c->fwd.ntasks, OP_RR, nullptr));
     CgArgs g = no_cg();
     g.rdot = c->r.p;
     g.part = c->part.p;
     g.sc = sc;
     ICCG_CHECK((launch_sweep<false, SW_DOT_BWD>(c, ytmp(c), c->z.p, g)));
-    ICCG_CHECK(launch_reduce(c, c->bwd.ntasks, OP_BETA, nullptr));
+    hipLaunchKernelGGL(k_reduce_rr_beta, dim3(1), dim3(kReduceThreads), 0, c->work, c->part_rr.p,
+                       c->fwd.ntasks, c->part.p, c->bwd.ntasks, sc, c->hist.p);
+    HIP_CHECK(hipGetLastError());
     return ICCG_OK;
 }
 
@@ -984,6 +1067,7 @@ int upload_sweep(iccg_ctx *c, const SweepPlan &plan, DevSweep &d) {
     d.max_width = plan.max_width;
     d.kmax = plan.max_width <= 4 ? 4 : plan.max_width <= 8 ? 8 : plan.max_width <= 16 ? 16 : 32;
     d.color_task_ptr = plan.color_task_ptr;
+    d.color_layout = plan.color_layout;
     ICCG_CHECK(d.tasks.upload(plan.tasks.data(), plan.tasks.size(), c->work));
     ICCG_CHECK(d.dep_ptr.upload(plan.dep_ptr.data(), plan.dep_ptr.size(), c->work));
     d.ndeps = static_cast<long long>(plan.deps.size());
@@ -1121,6 +1205,7 @@ int upload_setup(iccg_ctx *c, int n, const int *rowptr, const int *col, const do
     c->vec_blocks = round8(grid_for(n, kVecThreads, kMaxVecBlocks));
     const int np = std::max({c->spmv_blocks, c->vec_blocks, c->bwd.ntasks, c->fwd.ntasks, 1});
     ICCG_CHECK(c->part.alloc(np));
+    ICCG_CHECK(c->part_rr.alloc(std::max(c->fwd.ntasks, 1)));
     ICCG_CHECK(c->scal.alloc(1));
     ICCG_CHECK(c->dint.alloc(1));
     ICCG_CHECK(c->sweep_err.alloc(1));
@@ -1200,7 +1285,10 @@ int solve_impl(iccg_ctx *c, const double *b, double *x, double tol, int maxit, i
             ICCG_CHECK(read_scalars(c));
         }
     }
-    // true residual
+    // the last iteration's x step, then the true residual
+    hipLaunchKernelGGL(k_axpy_alpha, dim3(c->vec_blocks), dim3(kVecThreads), 0, s, n, c->x.p, c->p.p,
+                       c->scal.p);
+    HIP_CHECK(hipGetLastError());
     ICCG_CHECK(launch_spmv(c, SP_RESID, c->x.p, c->q.p, c->b.p, nullptr));
     ICCG_CHECK(launch_reduce(c, c->spmv_blocks, OP_TRUE, nullptr));
     HIP_CHECK(hipMemcpyAsync(x, c->x.p, sizeof(double) * n, hipMemcpyDeviceToDevice, s));

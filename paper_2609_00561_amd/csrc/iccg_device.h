@@ -86,6 +86,7 @@ struct DevSweep {
     int max_width = 0;
     int kmax = 4;                      // register slots per row in k_sweep
     std::vector<int> color_task_ptr;
+    std::vector<ColorLayout> color_layout;
     DevArray<TaskRec> tasks;
     DevArray<Chunk> chunks;
     DevArray<uint32_t> meta;
@@ -171,7 +172,7 @@ struct iccg_ctx {
     bool has_factor = false;
     DevArray<double> x, r, z, p, q, b, y64;
     DevArray<float> y32;
-    DevArray<double> part, hist;
+    DevArray<double> part, part_rr, hist;   // partial sums; part_rr: ||r||^2 per forward task
     DevArray<DevScalars> scal;
     DevArray<int> dint;
     DevArray<int> sweep_err;       // set by a sweep wait that exceeded its spin limit
