@@ -241,11 +241,13 @@ __global__ __launch_bounds__(64) void k_spmv(int n, int nslices, const int *__re
         const int row = sl * 64 + lane;
         int cc[WMAX];
         double vv[WMAX], xv[WMAX];
+        // the matrix streams through once (non-temporal: it should not push
+        // the gathered vector out of L2)
 #pragma unroll
         for (int k = 0; k < WMAX; ++k)
             if (k < w) {
-                cc[k] = col[off + k * 64];
-                vv[k] = val[off + k * 64];
+                cc[k] = __builtin_nontemporal_load(col + off + k * 64);
+                vv[k] = __builtin_nontemporal_load(val + off + k * 64);
             }
         double own_x = 0.0, own_b = 0.0;
         if (row < n) {
@@ -495,15 +497,17 @@ __device__ __forceinline__ void sweep_chunk(const Chunk &ch, const uint32_t *__r
     // the first dependency a lane waits for, ahead of the chunk's loads
     const int pre = wait.pre();
     if (active) {
-        // every independent load of the chunk first, so they overlap
+        // every independent load of the chunk first, so they overlap; the
+        // schedule streams through once (non-temporal: it should not push the
+        // gathered values out of L2)
 #pragma unroll
         for (int k = 0; k < KMAX; ++k)
             if (k < W) {
-                vv[k] = sval[base + k * nr];
-                cc[k] = scol[base + k * nr];
+                vv[k] = __builtin_nontemporal_load(sval + base + k * nr);
+                cc[k] = __builtin_nontemporal_load(scol + base + k * nr);
             }
-        m = meta[i];
-        dinv = inv[i];
+        m = __builtin_nontemporal_load(meta + i);
+        dinv = __builtin_nontemporal_load(inv + i);
         if (MODE == SW_CG_FWD) {
             const double ri = cg.r[i] - alpha * cg.q[i];
             cg.r[i] = ri;
