@@ -221,9 +221,7 @@ enum SpmvMode : int { SP_PLAIN = 0, SP_RESID = 1 };
 // row are loaded into registers at once, then all gathers, then the row sum in
 // ascending column order.
 template <int MODE, int WMAX>
-__global__ __launch_bounds__(64) void k_spmv(int n, int nslices, const int *__restrict__ slice_order,
-                                             const int *__restrict__ slice_off,
-                                             const int *__restrict__ slice_w,
+__global__ __launch_bounds__(64) void k_spmv(int n, int nslices, const int4 *__restrict__ slices,
                                              const int *__restrict__ col,
                                              const double *__restrict__ val,
                                              const double *__restrict__ x,
@@ -236,8 +234,10 @@ __global__ __launch_bounds__(64) void k_spmv(int n, int nslices, const int *__re
     const int wg = xcd_remap(blockIdx.x, gridDim.x);
     double acc = 0.0;
     for (int lg = wg; lg < nslices; lg += gridDim.x) {
-        const int sl = slice_order[lg];
-        const int off = slice_off[sl] + lane, w = slice_w[sl];
+        // launch-ordered slice record: (slice, first slot, width)
+        const int4 rec = slices[lg];
+        const int sl = rec.x;
+        const int off = rec.y + lane, w = rec.z;
         const int row = sl * 64 + lane;
         int cc[WMAX];
         double vv[WMAX], xv[WMAX];
@@ -302,17 +302,23 @@ __global__ __launch_bounds__(kVecThreads) void k_fill(int n, double *__restrict_
 // x += alpha p (the previous iteration's step, alpha still in the scalar
 // block), then p = z + beta p.  alpha = beta = 0 and p = 0 before the first
 // iteration.
-__global__ __launch_bounds__(kVecThreads) void k_update_p(int n, double *__restrict__ x,
-                                                          double *__restrict__ p,
-                                                          const double *__restrict__ z,
-                                                          const DevScalars *sc) {
+// Rows are visited slice by slice in the SpMV's launch order and XCD mapping,
+// so the p values each XCD writes are the ones its SpMV workgroups gather.
+__global__ __launch_bounds__(64) void k_update_p(int n, int nslices,
+                                                 const int *__restrict__ slice_order,
+                                                 double *__restrict__ x, double *__restrict__ p,
+                                                 const double *__restrict__ z,
+                                                 const DevScalars *sc) {
     if (sc->done != DONE_RUNNING) return;
     const double alpha = sc->alpha, beta = sc->beta;
     const int wg = xcd_remap(blockIdx.x, gridDim.x);
-    for (int i = wg * kVecThreads + threadIdx.x; i < n; i += gridDim.x * kVecThreads) {
-        const double pi = p[i];
-        x[i] = x[i] + alpha * pi;
-        p[i] = z[i] + beta * pi;
+    for (int lg = wg; lg < nslices; lg += gridDim.x) {
+        const int i = slice_order[lg] * 64 + static_cast<int>(threadIdx.x);
+        if (i < n) {
+            const double pi = p[i];
+            x[i] = x[i] + alpha * pi;
+            p[i] = z[i] + beta * pi;
+        }
     }
 }
 
@@ -573,38 +579,25 @@ __global__ __launch_bounds__(64) void k_sweep(const TaskRec *__restrict__ tasks,
                                               const int *__restrict__ scol,
                                               const F *__restrict__ sval,
                                               const F *__restrict__ inv, int task_base,
-                                              int ntasks_color, ColorLayout lay,
-                                              const TIn *__restrict__ in,
+                                              int ntasks_color, const TIn *__restrict__ in,
                                               TOut *__restrict__ out, CgArgs cg) {
     if (cg.sc && cg.sc->done != DONE_RUNNING) return;
     __shared__ F ys[kChunkRows];
-    const int local = xcd_remap(blockIdx.x, ntasks_color);
-    const int task = task_base + local;
+    const int task = task_base + xcd_remap(blockIdx.x, ntasks_color);
     const double alpha = (MODE == SW_CG_FWD) ? cg.sc->alpha : 0.0;
     double dacc = 0.0;
     F yv;
     uint32_t m;
-    if (lay.uniform) {
-        // the chunk follows from the launch constants: no task record to wait for
-        Chunk ch;
-        ch.row0 = lay.row0 + kChunkRows * local;
-        ch.off = lay.off + kChunkRows * lay.width * local;
-        ch.shape = min(kChunkRows, lay.row0 + lay.rows - ch.row0) | (lay.width << 16);
-        ch.depth = lay.depth;
+    const TaskRec tr = tasks[task];
+    sweep_chunk<F, FWD, KMAX, MODE, TIn, TOut>(tr.first, meta, scol, sval, inv, in, out, cg, alpha,
+                                               ys, dacc, NoWait(), PlainMem(), yv, m);
+    const int nchunks = tr.c1 - tr.c0;
+    for (int q = 1; q < nchunks; ++q) {
+        // later chunks of this task read earlier chunks' results from memory
+        __syncthreads();
+        const Chunk ch = chunks[FWD ? tr.c0 + q : tr.c1 - 1 - q];
         sweep_chunk<F, FWD, KMAX, MODE, TIn, TOut>(ch, meta, scol, sval, inv, in, out, cg, alpha,
                                                    ys, dacc, NoWait(), PlainMem(), yv, m);
-    } else {
-        const TaskRec tr = tasks[task];
-        sweep_chunk<F, FWD, KMAX, MODE, TIn, TOut>(tr.first, meta, scol, sval, inv, in, out, cg,
-                                                   alpha, ys, dacc, NoWait(), PlainMem(), yv, m);
-        const int nchunks = tr.c1 - tr.c0;
-        for (int q = 1; q < nchunks; ++q) {
-            // later chunks of this task read earlier chunks' results from memory
-            __syncthreads();
-            const Chunk ch = chunks[FWD ? tr.c0 + q : tr.c1 - 1 - q];
-            sweep_chunk<F, FWD, KMAX, MODE, TIn, TOut>(ch, meta, scol, sval, inv, in, out, cg, alpha,
-                                                       ys, dacc, NoWait(), PlainMem(), yv, m);
-        }
     }
     if (MODE != SW_APPLY) {
         const double tsum = wave_sum(dacc);
@@ -775,7 +768,7 @@ int launch_spmv(iccg_ctx *c, int mode, const double *x, double *y, const double 
                 const DevScalars *sc) {
     dim3 grid(c->spmv_blocks), block(64);
     if (c->prof) c->prof->begin(c->work);
-#define SPMV_ARGS c->n, c->nslices, c->sell_order.p, c->sell_off.p, c->sell_w.p, c->sell_col.p, c->sell_val.p, x, y, b, c->part.p, sc
+#define SPMV_ARGS c->n, c->nslices, c->sell_rec.p, c->sell_col.p, c->sell_val.p, x, y, b, c->part.p, sc
 #define SPMV_W(M)                                                                              \
     switch (c->sell_wmax) {                                                                    \
         case 8: hipLaunchKernelGGL((k_spmv<M, 8>), grid, block, 0, c->work, SPMV_ARGS); break;   \
@@ -889,7 +882,7 @@ int launch_sweep_t(iccg_ctx *c, const void *in, void *out, const CgArgs &cg) {
         HIP_CHECK(hipGetLastError());
         return ICCG_OK;
     }
-#define SWEEP_ARGS a.tasks, a.chunks, a.meta, a.scol, a.sval, a.inv, t0, t1 - t0, d.color_layout[col], pin, pout, cg
+#define SWEEP_ARGS a.tasks, a.chunks, a.meta, a.scol, a.sval, a.inv, t0, t1 - t0, pin, pout, cg
     if (c->prof) c->prof->begin(c->work);
     int launched = 0;
     for (int step = 0; step < c->ncolors; ++step) {
@@ -983,8 +976,8 @@ int enqueue_iteration(iccg_ctx *c, long long j) {
     (void)j;
     DevScalars *sc = c->scal.p;
     double *p = c->p.p;
-    hipLaunchKernelGGL(k_update_p, dim3(c->vec_blocks), dim3(kVecThreads), 0, c->work, c->n, c->x.p, p,
-                       c->z.p, sc);
+    hipLaunchKernelGGL(k_update_p, dim3(c->spmv_blocks), dim3(64), 0, c->work, c->n, c->nslices,
+                       c->sell_order.p, c->x.p, p, c->z.p, sc);
     HIP_CHECK(hipGetLastError());
     ICCG_CHECK(launch_spmv(c, SP_PLAIN, p, c->q.p, nullptr, sc));
     ICCG_CHECK(launch_reduce(c, c->spmv_blocks, OP_ALPHA, nullptr));
@@ -1071,7 +1064,6 @@ int upload_sweep(iccg_ctx *c, const SweepPlan &plan, DevSweep &d) {
     d.max_width = plan.max_width;
     d.kmax = plan.max_width <= 4 ? 4 : plan.max_width <= 8 ? 8 : plan.max_width <= 16 ? 16 : 32;
     d.color_task_ptr = plan.color_task_ptr;
-    d.color_layout = plan.color_layout;
     ICCG_CHECK(d.tasks.upload(plan.tasks.data(), plan.tasks.size(), c->work));
     ICCG_CHECK(d.dep_ptr.upload(plan.dep_ptr.data(), plan.dep_ptr.size(), c->work));
     d.ndeps = static_cast<long long>(plan.deps.size());
@@ -1195,9 +1187,15 @@ int upload_setup(iccg_ctx *c, int n, const int *rowptr, const int *col, const do
         ICCG_CHECK(v->alloc(n));
 
     c->nslices = static_cast<int>(hs.sell.slice_off.size());
-    ICCG_CHECK(c->sell_off.upload(hs.sell.slice_off.data(), hs.sell.slice_off.size(), s));
+    {
+        std::vector<int4> rec(c->nslices);
+        for (int lg = 0; lg < c->nslices; ++lg) {
+            const int sl = hs.sell.order[lg];
+            rec[lg] = make_int4(sl, hs.sell.slice_off[sl], hs.sell.slice_width[sl], 0);
+        }
+        ICCG_CHECK(c->sell_rec.upload(rec.data(), rec.size(), s));
+    }
     ICCG_CHECK(c->sell_order.upload(hs.sell.order.data(), hs.sell.order.size(), s));
-    ICCG_CHECK(c->sell_w.upload(hs.sell.slice_width.data(), hs.sell.slice_width.size(), s));
     ICCG_CHECK(c->sell_col.upload(hs.sell.col.data(), hs.sell.col.size(), s));
     ICCG_CHECK(c->sell_val.upload(hs.sell.val.data(), hs.sell.val.size(), s));
     // grids are multiples of 8 so the XCD remap spreads whole ranges

@@ -86,7 +86,6 @@ struct DevSweep {
     int max_width = 0;
     int kmax = 4;                      // register slots per row in k_sweep
     std::vector<int> color_task_ptr;
-    std::vector<ColorLayout> color_layout;
     DevArray<TaskRec> tasks;
     DevArray<Chunk> chunks;
     DevArray<uint32_t> meta;
@@ -180,7 +179,8 @@ struct iccg_ctx {
     int h_err = 0;
     int nslices = 0;                // sliced ELL copy of A' for the SpMV
     int sell_wmax = 8;              // register slots per row in k_spmv
-    DevArray<int> sell_order, sell_off, sell_w, sell_col;
+    DevArray<int4> sell_rec;        // per launch position: slice, first slot, width
+    DevArray<int> sell_order, sell_col;
     DevArray<double> sell_val;
     int spmv_blocks = 1, vec_blocks = 1;
     hipGraphExec_t graph = nullptr;

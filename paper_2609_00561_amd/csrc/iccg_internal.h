@@ -62,23 +62,12 @@ inline uint32_t pack_meta(int n_ext, int n_int, int level) {
            (static_cast<uint32_t>(level) << 24);
 }
 
-// A color whose tasks are single chunks tiling its rows in 64-row pieces
-// (the last may be shorter), all laid out with one slot width: chunk k starts
-// at row row0 + 64k and slot off + 64*width*k, so a launch needs no task
-// records (uniform = 0 otherwise).
-struct ColorLayout {
-    int32_t uniform;
-    int32_t row0, rows;
-    int32_t off, width, depth;
-};
-
 // One sweep direction.  Forward: row i uses L_ij, j < i; chunks of a task run
 // in ascending order, colors ascending.  Backward: row i uses (L^T)_ij = L_ji,
 // j > i; chunks of a task run in descending order, colors descending.
 struct SweepPlan {
     bool forward = true;
     std::vector<int> color_task_ptr;   // ncolors+1, tasks of each color
-    std::vector<ColorLayout> color_layout;   // ncolors
     std::vector<int> task_chunk_ptr;   // ntasks+1
     std::vector<TaskRec> tasks;        // ntasks
     std::vector<Chunk> chunks;

@@ -62,41 +62,11 @@ int build_sweep_plan(bool forward, int n, const int *rowptr, const int *col, con
         out.color_task_ptr.push_back(static_cast<int>(out.task_chunk_ptr.size()) - 1);
     }
 
-    // colors whose single-chunk tasks tile the rows in 64-row pieces get one
-    // slot width (the color's widest row in this triangle)
-    out.color_layout.assign(ncolors, ColorLayout{0, 0, 0, 0, 0, 0});
-    std::vector<int> chunk_color(chunk_rows.size(), 0);
-    for (int c = 0; c < ncolors; ++c) {
-        const int t0 = out.color_task_ptr[c], t1 = out.color_task_ptr[c + 1];
-        const int crow0 = block_ptr[color_ptr[c]], crows = block_ptr[color_ptr[c + 1]] - crow0;
-        bool uni = t1 > t0;
-        for (int t = t0; t < t1 && uni; ++t) {
-            const int ch = out.task_chunk_ptr[t];
-            if (out.task_chunk_ptr[t + 1] != ch + 1) uni = false;
-            const int k = t - t0;
-            if (chunk_rows[ch].first != crow0 + kChunkRows * k) uni = false;
-            if (t + 1 < t1 && chunk_rows[ch].second - chunk_rows[ch].first != kChunkRows) uni = false;
-        }
-        for (int t = t0; t < t1; ++t)
-            for (int ch = out.task_chunk_ptr[t]; ch < out.task_chunk_ptr[t + 1]; ++ch) chunk_color[ch] = c;
-        if (!uni) continue;
-        int w = 0;
-        for (int i = crow0; i < crow0 + crows; ++i) {
-            int cnt = 0;
-            for (int k = rowptr[i]; k < rowptr[i + 1]; ++k)
-                if (forward ? (col[k] < i) : (col[k] > i)) ++cnt;
-            w = std::max(w, cnt);
-        }
-        out.color_layout[c] = ColorLayout{1, crow0, crows, 0, w, 1};
-    }
-
     // 2. per chunk: classify entries, levels, slot layout
     long long nslots = 0;
     RowEntries rows[kChunkRows];
     int level[kChunkRows];
-    for (size_t chi = 0; chi < chunk_rows.size(); ++chi) {
-        const auto &cr = chunk_rows[chi];
-        ColorLayout &cl = out.color_layout[chunk_color[chi]];
+    for (const auto &cr : chunk_rows) {
         const int r0 = cr.first, r1 = cr.second, nr = r1 - r0;
         int width = 0, depth = 0;
         for (int step = 0; step < nr; ++step) {
@@ -122,11 +92,6 @@ int build_sweep_plan(bool forward, int n, const int *rowptr, const int *col, con
             width = std::max(width, static_cast<int>(re.ext.size() + re.inn.size()));
             depth = std::max(depth, lev + 1);
             out.meta[i] = pack_meta(static_cast<int>(re.ext.size()), static_cast<int>(re.inn.size()), lev);
-        }
-        if (cl.uniform) {
-            if (r0 == cl.row0) cl.off = static_cast<int32_t>(nslots);
-            width = cl.width;
-            cl.depth = std::max(cl.depth, depth);
         }
         if (nslots + static_cast<long long>(width) * nr >= (1LL << 31))
             return set_error(ICCG_EINVAL, "substitution schedule exceeds 2^31 slots");
