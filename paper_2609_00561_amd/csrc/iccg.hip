@@ -216,6 +216,7 @@ __global__ void k_init_scalars(DevScalars *sc, double tol, int maxit, int hist_c
 //   SP_RESID: y = b - A x, partial (y, y)
 // ---------------------------------------------------------------------------
 enum SpmvMode : int { SP_PLAIN = 0, SP_RESID = 1 };
+constexpr int kSpmvSlicesPerWave = 2;
 
 // One wavefront workgroup per slice (grid-stride over slices); WMAX slots of a
 // row are loaded into registers at once, then all gathers, then the row sum in
@@ -230,49 +231,67 @@ __global__ __launch_bounds__(64) void k_spmv(int n, int nslices, const int4 *__r
                                              double *__restrict__ part,
                                              const DevScalars *sc) {
     if (sc && sc->done != DONE_RUNNING) return;
+    constexpr int U = kSpmvSlicesPerWave;
     const int lane = threadIdx.x;
     const int wg = xcd_remap(blockIdx.x, gridDim.x);
     double acc = 0.0;
-    for (int lg = wg; lg < nslices; lg += gridDim.x) {
-        // launch-ordered slice record: (slice, first slot, width)
-        const int4 rec = slices[lg];
-        const int sl = rec.x;
-        const int off = rec.y + lane, w = rec.z;
-        const int row = sl * 64 + lane;
-        int cc[WMAX];
-        double vv[WMAX], xv[WMAX];
+    for (int lg0 = wg * U; lg0 < nslices; lg0 += gridDim.x * U) {
+        // U consecutive launch positions at once, so one wavefront has all of
+        // their loads in flight together.  Launch-ordered slice record:
+        // (slice, first slot, width).
+        int off[U], w[U], row[U];
+        int cc[U][WMAX];
+        double vv[U][WMAX], xv[U][WMAX], own_x[U], own_b[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int4 rec = lg0 + u < nslices ? slices[lg0 + u] : make_int4(0, 0, 0, 0);
+            off[u] = rec.y + lane;
+            w[u] = rec.z;
+            row[u] = lg0 + u < nslices ? rec.x * 64 + lane : n;
+        }
         // the matrix streams through once (non-temporal: it should not push
         // the gathered vector out of L2)
 #pragma unroll
-        for (int k = 0; k < WMAX; ++k)
-            if (k < w) {
-                cc[k] = __builtin_nontemporal_load(col + off + k * 64);
-                vv[k] = __builtin_nontemporal_load(val + off + k * 64);
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int k = 0; k < WMAX; ++k)
+                if (k < w[u]) {
+                    cc[u][k] = __builtin_nontemporal_load(col + off[u] + k * 64);
+                    vv[u][k] = __builtin_nontemporal_load(val + off[u] + k * 64);
+                }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            own_x[u] = 0.0;
+            own_b[u] = 0.0;
+            if (row[u] < n) {
+                own_x[u] = x[row[u]];
+                if (MODE == SP_RESID) own_b[u] = b[row[u]];
             }
-        double own_x = 0.0, own_b = 0.0;
-        if (row < n) {
-            own_x = x[row];
-            if (MODE == SP_RESID) own_b = b[row];
         }
 #pragma unroll
-        for (int k = 0; k < WMAX; ++k)
-            if (k < w) xv[k] = x[cc[k] < 0 ? 0 : cc[k]];
-        double sum = 0.0;
+        for (int u = 0; u < U; ++u)
 #pragma unroll
-        for (int k = 0; k < WMAX; ++k)
-            if (k < w) sum = (cc[k] >= 0) ? sum + vv[k] * xv[k] : sum;
-        for (int k = WMAX; k < w; ++k) {
-            const int c = col[off + k * 64];
-            if (c >= 0) sum += val[off + k * 64] * x[c];
-        }
-        if (row < n) {
-            if (MODE == SP_PLAIN) {
-                y[row] = sum;
-                acc += own_x * sum;
-            } else {
-                const double rv = own_b - sum;
-                y[row] = rv;
-                acc += rv * rv;
+            for (int k = 0; k < WMAX; ++k)
+                if (k < w[u]) xv[u][k] = x[cc[u][k] < 0 ? 0 : cc[u][k]];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            double sum = 0.0;
+#pragma unroll
+            for (int k = 0; k < WMAX; ++k)
+                if (k < w[u]) sum = (cc[u][k] >= 0) ? sum + vv[u][k] * xv[u][k] : sum;
+            for (int k = WMAX; k < w[u]; ++k) {
+                const int c = col[off[u] + k * 64];
+                if (c >= 0) sum += val[off[u] + k * 64] * x[c];
+            }
+            if (row[u] < n) {
+                if (MODE == SP_PLAIN) {
+                    y[row[u]] = sum;
+                    acc += own_x[u] * sum;
+                } else {
+                    const double rv = own_b[u] - sum;
+                    y[row[u]] = rv;
+                    acc += rv * rv;
+                }
             }
         }
     }
@@ -976,7 +995,7 @@ int enqueue_iteration(iccg_ctx *c, long long j) {
     (void)j;
     DevScalars *sc = c->scal.p;
     double *p = c->p.p;
-    hipLaunchKernelGGL(k_update_p, dim3(c->spmv_blocks), dim3(64), 0, c->work, c->n, c->nslices,
+    hipLaunchKernelGGL(k_update_p, dim3(c->nslices), dim3(64), 0, c->work, c->n, c->nslices,
                        c->sell_order.p, c->x.p, p, c->z.p, sc);
     HIP_CHECK(hipGetLastError());
     ICCG_CHECK(launch_spmv(c, SP_PLAIN, p, c->q.p, nullptr, sc));
@@ -1203,7 +1222,8 @@ int upload_setup(iccg_ctx *c, int n, const int *rowptr, const int *col, const do
     int wmax = 0;
     for (int w : hs.sell.slice_width) wmax = std::max(wmax, w);
     c->sell_wmax = wmax <= 8 ? 8 : wmax <= 16 ? 16 : 32;
-    c->spmv_blocks = c->nslices;   // one wavefront per slice, in launch order
+    // one wavefront per kSpmvSlicesPerWave slices, in launch order
+    c->spmv_blocks = (c->nslices + kSpmvSlicesPerWave - 1) / kSpmvSlicesPerWave;
     c->vec_blocks = round8(grid_for(n, kVecThreads, kMaxVecBlocks));
     const int np = std::max({c->spmv_blocks, c->vec_blocks, c->bwd.ntasks, c->fwd.ntasks, 1});
     ICCG_CHECK(c->part.alloc(np));
