@@ -173,10 +173,10 @@ def parse():
     ap.add_argument("--no-leiden", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-iters", type=int, default=40)
+    ap.add_argument("--cpu-iters", type=int, default=100)
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--learned-matrices", type=int, default=256)
-    ap.add_argument("--learned-epochs", type=int, default=3)
+    ap.add_argument("--learned-epochs", type=int, default=4)
     ap.add_argument("--seed", type=int, default=42)
     ap.add_argument("--traffic-run", action="store_true",
                     help="run only the program profiled by the --pmc traffic passes")
@@ -354,6 +354,7 @@ def main():
             Ak, _ = _synth.workload("lognormal7_32", k)
             ctxs.append(learned.build_context(Ak, 64)[0])
         t_setup = time.time() - tl0
+        evals = []
         with iccg.Network(learned.init_params(0)) as net:
             tt = time.time()
             hist = learned.train(net, ctxs, args.learned_epochs, lr=1e-3, seed=0, log=log)
@@ -361,18 +362,38 @@ def main():
             t_train = time.time() - tt
             for c_ in ctxs:
                 c_.close()
+            # unseen seeds of the training family at 64^3 and 128^3, then the
+            # timed matrix itself
+            for grid in ("lognormal7_64", "lognormal7_128"):
+                Ae, be = _synth.workload(grid, 10000)
+                ce, oe = learned.build_context(Ae, 64)
+                with ce:
+                    ev = learned.solve_both(net, ce, torch.tensor(be[oe.perm], device=dev), tol=args.tol)
+                ev["matrix"] = f"{grid} seed 10000 (unseen), ABMC s=64"
+                evals.append(ev)
+                log(f"[bench] learned form on {ev['matrix']}: {ev}")
             ev = learned.solve_both(net, ctx, torch.tensor(bp, device=dev), tol=args.tol)
+            ev["matrix"] = f"{args.workload} (timed matrix), ABMC s={s_best}"
+            evals.append(ev)
+
+        def _fmt(ev):
+            return {
+                "matrix": ev["matrix"],
+                "plain_iters": ev["plain_iters"], "plain_ms": round(ev["plain_ms"], 3),
+                "learned_iters": ev.get("learned_iters"),
+                "learned_ms": round(ev["learned_ms"], 3) if "learned_ms" in ev else None,
+                "inference_ms": round(ev["infer_ms"], 3), "feature_setup_ms": round(ev["setup_ms"], 3),
+                "pivot_ok": ev["pivot_ok"],
+                "kept": ev["kept"], "x_rel_diff_vs_plain": ev.get("x_rel_diff"),
+                "speedup_vs_fp64_incl_inference": (round(ev["plain_ms"] / (ev["learned_ms"] + ev["infer_ms"]), 3)
+                                                   if "learned_ms" in ev else None),
+            }
         out["learned"] = {
             "train": {"matrices": args.learned_matrices, "grid": "32^3", "epochs": args.learned_epochs,
+                      "probes": "8 per step, IC(0)-smoothed Gaussian",
                       "probe_loss_by_epoch": [round(v, 5) for v in hist],
                       "train_s": round(t_train, 2), "setup_s": round(t_setup, 2)},
-            "plain_iters": ev["plain_iters"], "plain_ms": round(ev["plain_ms"], 3),
-            "learned_iters": ev.get("learned_iters"),
-            "learned_ms": round(ev["learned_ms"], 3) if "learned_ms" in ev else None,
-            "inference_ms": round(ev["infer_ms"], 3), "pivot_ok": ev["pivot_ok"], "kept": ev["kept"],
-            "x_rel_diff_vs_plain": ev.get("x_rel_diff"),
-            "speedup_vs_fp64_incl_inference": (round(ev["plain_ms"] / (ev["learned_ms"] + ev["infer_ms"]), 3)
-                                               if "learned_ms" in ev else None),
+            "eval": [_fmt(ev) for ev in evals],
         }
         log(f"[bench] learned form: {out['learned']}")
 
