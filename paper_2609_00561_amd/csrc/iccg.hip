@@ -429,6 +429,9 @@ struct SweepArgs {
 // part[task] = sum of rdot_i z_i.
 enum SweepMode : int { SW_APPLY = 0, SW_CG_FWD = 1, SW_DOT_BWD = 2 };
 
+// Tasks (wavefronts) per workgroup of a per-color sweep launch.
+constexpr int kSweepWaves = 1;
+
 struct CgArgs {
     double *r;
     const double *q;
@@ -509,7 +512,7 @@ __device__ __forceinline__ void sweep_chunk(const Chunk &ch, const uint32_t *__r
                                             const CgArgs &cg, double alpha, F *ys, double &dacc,
                                             const Wait &wait, const Mem &mem, F &y_out,
                                             uint32_t &m_out) {
-    const int t = threadIdx.x;
+    const int t = static_cast<int>(threadIdx.x) & (kChunkRows - 1);
     const int nr = ch.shape & 0xffff, W = ch.shape >> 16;
     const bool active = t < nr;
     const int i = ch.row0 + t;
@@ -572,7 +575,12 @@ __device__ __forceinline__ void sweep_chunk(const Chunk &ch, const uint32_t *__r
             }
             ys[t] = s * dinv;
         }
-        __syncthreads();
+        // ys is this wavefront's own; its LDS operations execute in order,
+        // so the next level's reads see this level's writes (the fences keep
+        // the compiler from reordering them)
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
     }
     F yv = F(0);
     if (active) {
@@ -592,17 +600,24 @@ __device__ __forceinline__ void sweep_chunk(const Chunk &ch, const uint32_t *__r
 // level through LDS.  The per-row subtraction order is: before-chunk terms in
 // ascending column order, then in-chunk terms in ascending column order.
 template <typename F, bool FWD, int KMAX, int MODE, typename TIn, typename TOut>
-__global__ __launch_bounds__(64) void k_sweep(const TaskRec *__restrict__ tasks,
-                                              const Chunk *__restrict__ chunks,
-                                              const uint32_t *__restrict__ meta,
-                                              const int *__restrict__ scol,
-                                              const F *__restrict__ sval,
-                                              const F *__restrict__ inv, int task_base,
-                                              int ntasks_color, const TIn *__restrict__ in,
-                                              TOut *__restrict__ out, CgArgs cg) {
+__global__ __launch_bounds__(64 * kSweepWaves) void k_sweep(const TaskRec *__restrict__ tasks,
+                                                            const Chunk *__restrict__ chunks,
+                                                            const uint32_t *__restrict__ meta,
+                                                            const int *__restrict__ scol,
+                                                            const F *__restrict__ sval,
+                                                            const F *__restrict__ inv, int task_base,
+                                                            int ntasks_color, const TIn *__restrict__ in,
+                                                            TOut *__restrict__ out, CgArgs cg) {
     if (cg.sc && cg.sc->done != DONE_RUNNING) return;
-    __shared__ F ys[kChunkRows];
-    const int task = task_base + xcd_remap(blockIdx.x, ntasks_color);
+    __shared__ F ys_all[kSweepWaves][kChunkRows];
+    // kSweepWaves independent tasks per workgroup, one per wavefront (fewer
+    // workgroups to dispatch); consecutive tasks, so the XCD regions hold
+    const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) / 64);
+    const int nwg = (ntasks_color + kSweepWaves - 1) / kSweepWaves;
+    const int local = xcd_remap(blockIdx.x, nwg) * kSweepWaves + wave;
+    if (local >= ntasks_color) return;
+    F *ys = ys_all[wave];
+    const int task = task_base + local;
     const double alpha = (MODE == SW_CG_FWD) ? cg.sc->alpha : 0.0;
     double dacc = 0.0;
     F yv;
@@ -612,15 +627,18 @@ __global__ __launch_bounds__(64) void k_sweep(const TaskRec *__restrict__ tasks,
                                                ys, dacc, NoWait(), PlainMem(), yv, m);
     const int nchunks = tr.c1 - tr.c0;
     for (int q = 1; q < nchunks; ++q) {
-        // later chunks of this task read earlier chunks' results from memory
-        __syncthreads();
+        // later chunks of this task read earlier chunks' results from memory:
+        // this wavefront's stores complete before its next loads
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        __builtin_amdgcn_wave_barrier();
         const Chunk ch = chunks[FWD ? tr.c0 + q : tr.c1 - 1 - q];
         sweep_chunk<F, FWD, KMAX, MODE, TIn, TOut>(ch, meta, scol, sval, inv, in, out, cg, alpha,
                                                    ys, dacc, NoWait(), PlainMem(), yv, m);
     }
     if (MODE != SW_APPLY) {
         const double tsum = wave_sum(dacc);
-        if (threadIdx.x == 0) cg.part[task] = tsum;
+        if ((threadIdx.x & 63) == 0) cg.part[task] = tsum;
     }
 }
 
@@ -909,7 +927,7 @@ int launch_sweep_t(iccg_ctx *c, const void *in, void *out, const CgArgs &cg) {
         const int t0 = d.color_task_ptr[col], t1 = d.color_task_ptr[col + 1];
         if (t1 == t0) continue;
         ++launched;
-        const dim3 grid(t1 - t0), block(64);
+        const dim3 grid((t1 - t0 + kSweepWaves - 1) / kSweepWaves), block(64 * kSweepWaves);
         switch (d.kmax) {
             case 4: hipLaunchKernelGGL((k_sweep<F, FWD, 4, MODE, TIn, TOut>), grid, block, 0, c->work, SWEEP_ARGS); break;
             case 8: hipLaunchKernelGGL((k_sweep<F, FWD, 8, MODE, TIn, TOut>), grid, block, 0, c->work, SWEEP_ARGS); break;
