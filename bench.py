@@ -171,6 +171,7 @@ def parse():
     ap.add_argument("--block-sizes", default="8,16,32,64")
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--no-leiden", action="store_true")
+    ap.add_argument("--no-hybrid", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=100)
@@ -211,9 +212,10 @@ def main():
     A, b = synth.workload(args.workload, args.seed)
     log(f"[bench] workload {args.workload}: n={A.n} nnz={A.nnz} ({time.time() - t0:.1f}s)")
 
-    def make_ctx(order, precision="fp64"):
+    def make_ctx(order, precision="fp64", sweep_launch="per_color"):
         rp, cl, vl = iccg.iccg_permute(A, order.perm)
-        ctx = iccg.Context(rp, cl, vl, order.block_ptr, order.color_ptr, precision=precision)
+        ctx = iccg.Context(rp, cl, vl, order.block_ptr, order.color_ptr, precision=precision,
+                           sweep_launch=sweep_launch)
         ctx.ic0_factor()
         return ctx
 
@@ -272,6 +274,19 @@ def main():
         ctx.close()
 
     _, s_best, ctx, order, bp, _ = best
+    # the same ordering with the hybrid sweeps (one launch per large color,
+    # the small colors as one dataflow launch), reported beside; the timed
+    # run keeps one launch per color, which the profiles and counters cover
+    launch_mode = "per_color"
+    if not args.no_hybrid:
+        ctx_h = make_ctx(order, sweep_launch="hybrid")
+        _, times_h, res_h, _ = time_solves(ctx_h, bp, max(1, min(args.steps, 3)), 1)
+        ms_h = 1e3 * float(np.median(times_h))
+        log(f"[bench] ABMC s={s_best}, hybrid sweeps: {ms_h:.2f} ms")
+        sweep.append({"ordering": f"ABMC s={s_best}, hybrid sweeps", "n_b": order.nblocks,
+                      "n_c": order.ncolors, "iters": res_h["iters"], "ms": round(ms_h, 3),
+                      "relres_true": res_h["relres_true"]})
+        ctx_h.close()
     info = ctx.info()
     log(f"[bench] timed: ABMC s={s_best}, {args.warmup} warmup + {args.steps} steps")
     total, times, res, xd = time_solves(ctx, bp, args.steps, args.warmup)
@@ -321,7 +336,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: 3D 7-point lognormal(sigma=1) Poisson 128^3, "
                                f"b uniform[-1,1], seed {args.seed}",
-                   "n": A.n, "nnz": A.nnz, "ordering": f"ABMC s={s_best}",
+                   "n": A.n, "nnz": A.nnz, "ordering": f"ABMC s={s_best}", "sweep_launch": launch_mode,
                    "n_b": info["nblocks"], "n_c": nc, "tol": args.tol},
         "iters": res["iters"],
         "relres_true": res["relres_true"],

@@ -69,15 +69,20 @@ typedef struct {
     int   use_graph;    /* 1 = replay the iteration batch as a captured HIP graph  */
     int   sweep_launch; /* 0 = one kernel launch per color (default); 1 = one
                            persistent launch per sweep, each wavefront task waiting
-                           only for the earlier-color tasks it reads (same
-                           arithmetic, bit-identical results)                     */
+                           only for the earlier-color tasks it reads; 2 = hybrid:
+                           one launch per large color, and the small last colors
+                           of the forward sweep (first of the backward sweep) in
+                           one such dataflow launch.  Same arithmetic and
+                           bit-identical results in all three.                   */
     int   sweep_grid;   /* single-launch sweep: its workgroups, all of which must
                            be resident at once (0 = 8 per compute unit; otherwise
                            this many, bounded by the resident capacity and rounded
                            down to a multiple of 8, at least 8)                  */
+    int   flow_tail;    /* hybrid sweeps: at most this many tasks in the dataflow
+                           part (0 = 700)                                       */
 } iccg_options;
 
-/* Fills *opt with the defaults above (FP64, null stream, 32, 64, 1, 0, 0). */
+/* Fills *opt with the defaults above (FP64, null stream, 32, 64, 1, 0, 0, 0). */
 void iccg_default_options(iccg_options *opt);
 
 /* ------------------------------------------------------------------------ */

@@ -431,6 +431,9 @@ enum SweepMode : int { SW_APPLY = 0, SW_CG_FWD = 1, SW_DOT_BWD = 2 };
 
 // Tasks (wavefronts) per workgroup of a per-color sweep launch.
 constexpr int kSweepWaves = 1;
+// Hybrid sweeps run the small trailing colors, up to this many tasks in all,
+// as one dataflow launch (measured on 128^3: 700 beats 100 and 2200).
+constexpr int kFlowTailTasks = 700;
 
 struct CgArgs {
     double *r;
@@ -606,9 +609,12 @@ __global__ __launch_bounds__(64 * kSweepWaves) void k_sweep(const TaskRec *__res
                                                             const int *__restrict__ scol,
                                                             const F *__restrict__ sval,
                                                             const F *__restrict__ inv, int task_base,
-                                                            int ntasks_color, const TIn *__restrict__ in,
+                                                            int ntasks_color, int *bump,
+                                                            const TIn *__restrict__ in,
                                                             TOut *__restrict__ out, CgArgs cg) {
     if (cg.sc && cg.sc->done != DONE_RUNNING) return;
+    // bumps the epoch of a dataflow launch that follows in the stream
+    if (bump && blockIdx.x == 0 && threadIdx.x == 0) *bump += 1;
     __shared__ F ys_all[kSweepWaves][kChunkRows];
     // kSweepWaves independent tasks per workgroup, one per wavefront (fewer
     // workgroups to dispatch); consecutive tasks, so the XCD regions hold
@@ -669,6 +675,9 @@ struct FlowArgs {
     const int *deps;
     const int *wg_task;
     int ntasks;
+    int pos0, pos1;      // table positions this launch runs
+    int dep_done_below;  // dependencies with a smaller task id are already final
+    int *bump;           // if set, block 0 bumps this (the other sweep's) epoch
     int spin_limit;
     int *err;            // 1: spin limit, 2: placement
 };
@@ -697,6 +706,7 @@ struct FlowWait {
     __device__ void operator()(int first) const {
         for (int l = static_cast<int>(threadIdx.x); l < nd; l += 64) {
             const int dep = l < 64 ? first : fa->deps[d0 + l];
+            if (dep < fa->dep_done_below) continue;   // written by an earlier launch
             int spins = 0;
             while (true) {
                 const int v = remote ? __hip_atomic_load(fa->flag_rem + dep, __ATOMIC_RELAXED,
@@ -739,6 +749,7 @@ __global__ __launch_bounds__(64) void k_sweep_flow(const TaskRec *__restrict__ t
                                                    const TIn *__restrict__ in,
                                                    TOut *__restrict__ out, CgArgs cg) {
     if (cg.sc && cg.sc->done != DONE_RUNNING) return;
+    if (fa.bump && blockIdx.x == 0 && threadIdx.x == 0) *fa.bump += 1;
     __shared__ F ys[kChunkRows];
     const int epoch = *fa.epoch;
     const int xcc = xcc_id();
@@ -746,7 +757,7 @@ __global__ __launch_bounds__(64) void k_sweep_flow(const TaskRec *__restrict__ t
     const int word = (epoch << 4) | xcc;
     const __amdgpu_buffer_rsrc_t rs_out = make_rsrc(out, static_cast<long long>(n) * sizeof(TOut));
     const __amdgpu_buffer_rsrc_t rs_loc = make_rsrc(fa.flag_loc, 4LL * fa.ntasks);
-    for (int pos = blockIdx.x; pos < fa.ntasks; pos += gridDim.x) {
+    for (int pos = fa.pos0 + static_cast<int>(blockIdx.x); pos < fa.pos1; pos += gridDim.x) {
         const int task = fa.wg_task[pos];
         const TaskRec tr = tasks[task];
         const int kind = tr.kind_ndeps & 3, nchunks = tr.c1 - tr.c0;
@@ -872,9 +883,57 @@ int resident_grid(iccg_ctx *c, const void *kfn, int ntasks, int *grid) {
     return ICCG_OK;
 }
 
-// All colors of one sweep direction: one launch per color (colors ascending
-// for the forward sweep, descending for the backward sweep), or one launch for
-// all of them with per-task dependency waits.
+// One dataflow launch over the table positions [pos0, pos1) of a sweep.
+template <typename F, bool FWD, int MODE, typename TIn, typename TOut>
+int launch_flow(iccg_ctx *c, DevSweep &d, const SweepArgs<F> &a, int pos0, int pos1,
+                int dep_done_below, int *bump, const TIn *pin, TOut *pout, const CgArgs &cg) {
+    FlowArgs fa;
+    fa.epoch = d.epoch.p;
+    fa.flag_loc = d.flag_loc.p;
+    fa.flag_rem = d.flag_rem.p;
+    fa.dep_ptr = d.dep_ptr.p;
+    fa.deps = d.deps.p;
+    fa.wg_task = d.wg_task.p;
+    fa.ntasks = d.ntasks;
+    fa.pos0 = pos0;
+    fa.pos1 = pos1;
+    fa.dep_done_below = dep_done_below;
+    fa.bump = bump;
+    fa.spin_limit = 1 << 18;
+    fa.err = c->sweep_err.p;
+    const void *kfn = nullptr;
+    switch (d.kmax) {
+        case 4: kfn = reinterpret_cast<const void *>(&k_sweep_flow<F, FWD, 4, MODE, TIn, TOut>); break;
+        case 8: kfn = reinterpret_cast<const void *>(&k_sweep_flow<F, FWD, 8, MODE, TIn, TOut>); break;
+        case 16: kfn = reinterpret_cast<const void *>(&k_sweep_flow<F, FWD, 16, MODE, TIn, TOut>); break;
+        default: kfn = reinterpret_cast<const void *>(&k_sweep_flow<F, FWD, 32, MODE, TIn, TOut>); break;
+    }
+    int R = 0;
+    ICCG_CHECK(resident_grid(c, kfn, pos1 - pos0, &R));
+    c->last_resident = R;
+    const dim3 grid(R), block(64);
+#define FLOW_ARGS a.tasks, a.chunks, a.meta, a.scol, a.sval, a.inv, fa, c->n, pin, pout, cg
+    switch (d.kmax) {
+        case 4: hipLaunchKernelGGL((k_sweep_flow<F, FWD, 4, MODE, TIn, TOut>), grid, block, 0, c->work, FLOW_ARGS); break;
+        case 8: hipLaunchKernelGGL((k_sweep_flow<F, FWD, 8, MODE, TIn, TOut>), grid, block, 0, c->work, FLOW_ARGS); break;
+        case 16: hipLaunchKernelGGL((k_sweep_flow<F, FWD, 16, MODE, TIn, TOut>), grid, block, 0, c->work, FLOW_ARGS); break;
+        default: hipLaunchKernelGGL((k_sweep_flow<F, FWD, 32, MODE, TIn, TOut>), grid, block, 0, c->work, FLOW_ARGS); break;
+    }
+#undef FLOW_ARGS
+    HIP_CHECK(hipGetLastError());
+    return ICCG_OK;
+}
+
+// All colors of one sweep direction (colors ascending for the forward sweep,
+// descending for the backward sweep):
+//   per-color: one launch per color;
+//   single:    one dataflow launch for all of them;
+//   hybrid:    one launch per large color, and the small colors (the last
+//              ones of the forward sweep, the first ones of the backward
+//              sweep) in one dataflow launch.  The first forward launch bumps
+//              the forward epoch, the forward dataflow launch the backward
+//              one, so no launch is added (a backward sweep on its own gets
+//              its bump from the entry point).
 template <typename F, bool FWD, int MODE>
 int launch_sweep_t(iccg_ctx *c, const void *in, void *out, const CgArgs &cg) {
     using TIn = typename std::conditional<FWD, double, F>::type;
@@ -883,49 +942,21 @@ int launch_sweep_t(iccg_ctx *c, const void *in, void *out, const CgArgs &cg) {
     const SweepArgs<F> a = sweep_args<F>(c, d);
     const TIn *pin = static_cast<const TIn *>(in);
     TOut *pout = static_cast<TOut *>(out);
+    if (c->prof) c->prof->begin(c->work);
     if (c->opt.sweep_launch == 1) {
-        FlowArgs fa;
-        fa.epoch = d.epoch.p;
-        fa.flag_loc = d.flag_loc.p;
-        fa.flag_rem = d.flag_rem.p;
-        fa.dep_ptr = d.dep_ptr.p;
-        fa.deps = d.deps.p;
-        fa.wg_task = d.wg_task.p;
-        fa.ntasks = d.ntasks;
-        fa.spin_limit = 1 << 18;
-        fa.err = c->sweep_err.p;
         hipLaunchKernelGGL(k_bump_epoch, dim3(1), dim3(64), 0, c->work, d.epoch.p, cg.sc);
-        if (c->prof) c->prof->begin(c->work);
-        const void *kfn = nullptr;
-        switch (d.kmax) {
-            case 4: kfn = reinterpret_cast<const void *>(&k_sweep_flow<F, FWD, 4, MODE, TIn, TOut>); break;
-            case 8: kfn = reinterpret_cast<const void *>(&k_sweep_flow<F, FWD, 8, MODE, TIn, TOut>); break;
-            case 16: kfn = reinterpret_cast<const void *>(&k_sweep_flow<F, FWD, 16, MODE, TIn, TOut>); break;
-            default: kfn = reinterpret_cast<const void *>(&k_sweep_flow<F, FWD, 32, MODE, TIn, TOut>); break;
-        }
-        int R = 0;
-        ICCG_CHECK(resident_grid(c, kfn, d.ntasks, &R));
-        c->last_resident = R;
-        const dim3 grid(R), block(64);
-#define FLOW_ARGS a.tasks, a.chunks, a.meta, a.scol, a.sval, a.inv, fa, c->n, pin, pout, cg
-        switch (d.kmax) {
-            case 4: hipLaunchKernelGGL((k_sweep_flow<F, FWD, 4, MODE, TIn, TOut>), grid, block, 0, c->work, FLOW_ARGS); break;
-            case 8: hipLaunchKernelGGL((k_sweep_flow<F, FWD, 8, MODE, TIn, TOut>), grid, block, 0, c->work, FLOW_ARGS); break;
-            case 16: hipLaunchKernelGGL((k_sweep_flow<F, FWD, 16, MODE, TIn, TOut>), grid, block, 0, c->work, FLOW_ARGS); break;
-            default: hipLaunchKernelGGL((k_sweep_flow<F, FWD, 32, MODE, TIn, TOut>), grid, block, 0, c->work, FLOW_ARGS); break;
-        }
-#undef FLOW_ARGS
+        ICCG_CHECK((launch_flow<F, FWD, MODE>(c, d, a, 0, d.ntasks, 0, nullptr, pin, pout, cg)));
         if (c->prof) c->prof->end(c->work, FWD ? PK_FWD : PK_BWD);
-        HIP_CHECK(hipGetLastError());
         return ICCG_OK;
     }
-#define SWEEP_ARGS a.tasks, a.chunks, a.meta, a.scol, a.sval, a.inv, t0, t1 - t0, pin, pout, cg
-    if (c->prof) c->prof->begin(c->work);
+    // colors [tail, ncolors) run as one dataflow launch in the hybrid mode
+    const int tail = c->opt.sweep_launch == 2 ? c->flow_tail : c->ncolors;
+    const int tail_tasks = d.color_task_ptr[c->ncolors] - d.color_task_ptr[tail];
+#define SWEEP_ARGS a.tasks, a.chunks, a.meta, a.scol, a.sval, a.inv, t0, t1 - t0, bump, pin, pout, cg
     int launched = 0;
-    for (int step = 0; step < c->ncolors; ++step) {
-        const int col = FWD ? step : c->ncolors - 1 - step;
+    auto per_color = [&](int col, int *bump) -> int {
         const int t0 = d.color_task_ptr[col], t1 = d.color_task_ptr[col + 1];
-        if (t1 == t0) continue;
+        if (t1 == t0) return ICCG_OK;
         ++launched;
         const dim3 grid((t1 - t0 + kSweepWaves - 1) / kSweepWaves), block(64 * kSweepWaves);
         switch (d.kmax) {
@@ -934,10 +965,31 @@ int launch_sweep_t(iccg_ctx *c, const void *in, void *out, const CgArgs &cg) {
             case 16: hipLaunchKernelGGL((k_sweep<F, FWD, 16, MODE, TIn, TOut>), grid, block, 0, c->work, SWEEP_ARGS); break;
             default: hipLaunchKernelGGL((k_sweep<F, FWD, 32, MODE, TIn, TOut>), grid, block, 0, c->work, SWEEP_ARGS); break;
         }
+        HIP_CHECK(hipGetLastError());
+        return ICCG_OK;
+    };
+    if (FWD) {
+        for (int col = 0; col < tail; ++col)
+            ICCG_CHECK(per_color(col, col == 0 && tail_tasks > 0 ? d.epoch.p : nullptr));
+        if (tail_tasks > 0) {
+            if (tail == 0)
+                hipLaunchKernelGGL(k_bump_epoch, dim3(1), dim3(64), 0, c->work, d.epoch.p, cg.sc);
+            // positions of colors >= tail are the table's last tail_tasks
+            ICCG_CHECK((launch_flow<F, FWD, MODE>(c, d, a, d.ntasks - tail_tasks, d.ntasks,
+                                                   d.color_task_ptr[tail], c->bwd.epoch.p, pin, pout, cg)));
+            ++launched;
+        }
+    } else {
+        if (tail_tasks > 0) {
+            // the backward sweep starts with the small colors: the table's
+            // first tail_tasks positions, all of whose dependencies are inside
+            ICCG_CHECK((launch_flow<F, FWD, MODE>(c, d, a, 0, tail_tasks, 0, nullptr, pin, pout, cg)));
+            ++launched;
+        }
+        for (int col = tail - 1; col >= 0; --col) ICCG_CHECK(per_color(col, nullptr));
     }
-    if (c->prof) c->prof->end(c->work, FWD ? PK_FWD : PK_BWD, launched);
 #undef SWEEP_ARGS
-    HIP_CHECK(hipGetLastError());
+    if (c->prof) c->prof->end(c->work, FWD ? PK_FWD : PK_BWD, launched);
     return ICCG_OK;
 }
 
@@ -956,7 +1008,7 @@ int report_sweep_err(iccg_ctx *c, int err) {
 
 // fails loudly if a dependency wait of the single-launch sweep failed
 int check_sweep_err(iccg_ctx *c) {
-    if (c->opt.sweep_launch != 1) return ICCG_OK;
+    if (c->opt.sweep_launch == 0) return ICCG_OK;
     int err = 0;
     HIP_CHECK(hipMemcpyAsync(&err, c->sweep_err.p, sizeof(int), hipMemcpyDeviceToHost, c->work));
     HIP_CHECK(hipStreamSynchronize(c->work));
@@ -967,7 +1019,7 @@ int check_sweep_err(iccg_ctx *c) {
 // 2^27: before it could get there, flags and epochs are cleared (host path,
 // never inside a captured graph).  `sweeps` bounds the launches to come.
 int flow_guard(iccg_ctx *c, long long sweeps) {
-    if (c->opt.sweep_launch != 1) return ICCG_OK;
+    if (c->opt.sweep_launch == 0) return ICCG_OK;
     if (c->flow_sweeps + sweeps < (1LL << 26)) {
         c->flow_sweeps += sweeps;
         return ICCG_OK;
@@ -1212,6 +1264,18 @@ int upload_setup(iccg_ctx *c, int n, const int *rowptr, const int *col, const do
     ICCG_CHECK(c->tpos.upload(hs.tpos.data(), nnz, s));
     ICCG_CHECK(upload_sweep(c, hs.fwd, c->fwd));
     ICCG_CHECK(upload_sweep(c, hs.bwd, c->bwd));
+    // hybrid sweeps: the trailing colors (in forward order) holding at most
+    // kFlowTailTasks tasks together, if there are at least two of them
+    {
+        int tail = c->ncolors, total = 0;
+        while (tail > 0) {
+            const int t = c->fwd.color_task_ptr[tail] - c->fwd.color_task_ptr[tail - 1];
+            if (total + t > (c->opt.flow_tail > 0 ? c->opt.flow_tail : kFlowTailTasks)) break;
+            total += t;
+            --tail;
+        }
+        c->flow_tail = (c->ncolors - tail >= 2) ? tail : c->ncolors;
+    }
     ICCG_CHECK(c->lval.alloc(nnz));
     if (c->fp32()) {
         ICCG_CHECK(c->inv32.alloc(n));
@@ -1378,6 +1442,7 @@ void iccg_default_options(iccg_options *opt) {
     opt->use_graph = 1;
     opt->sweep_launch = 0;
     opt->sweep_grid = 0;
+    opt->flow_tail = 0;
 }
 
 const char *iccg_strerror(int st) {
@@ -1411,12 +1476,13 @@ int iccg_setup(iccg_ctx **out, int n, const int *rowptr, const int *col, const d
             return set_error(ICCG_EINVAL, "precision must be ICCG_FP64 or ICCG_FP32");
         if (c->opt.check_every < 1) c->opt.check_every = 1;
         if (c->opt.pack_rows < 1 || c->opt.pack_rows > kChunkRows) c->opt.pack_rows = kChunkRows;
-        if (c->opt.sweep_launch != 0 && c->opt.sweep_launch != 1)
-            return set_error(ICCG_EINVAL, "sweep_launch must be 0 or 1");
+        if (c->opt.sweep_launch < 0 || c->opt.sweep_launch > 2)
+            return set_error(ICCG_EINVAL, "sweep_launch must be 0, 1 or 2");
         if (c->opt.sweep_grid < 0) return set_error(ICCG_EINVAL, "sweep_grid must be >= 0");
+        if (c->opt.flow_tail < 0) return set_error(ICCG_EINVAL, "flow_tail must be >= 0");
         // the single-launch sweep addresses vectors and flags through 32-bit
         // buffer ranges
-        if (c->opt.sweep_launch == 1 && n >= (1 << 27))
+        if (c->opt.sweep_launch != 0 && n >= (1 << 27))
             return set_error(ICCG_EINVAL, "the single-launch sweep needs n < 2^27");
         HostSetup hs;
         ICCG_CHECK(validate(n, rowptr, col, val, nblocks, block_ptr, ncolors, color_ptr,
@@ -1545,6 +1611,9 @@ int ic_backward(iccg_ctx *c, const double *y, double *z) {
         if (y == z) return set_error(ICCG_EINVAL, "y and z must not alias");
         if (!c->has_factor) return set_error(ICCG_ESTATE, "no factor");
         ICCG_CHECK(flow_guard(c, 1));
+        // on its own, the backward sweep's dataflow part gets its epoch here
+        if (c->opt.sweep_launch == 2)
+            hipLaunchKernelGGL(k_bump_epoch, dim3(1), dim3(64), 0, c->work, c->bwd.epoch.p, nullptr);
         if (c->fp32()) {
             hipLaunchKernelGGL((k_convert<float, double>), dim3(c->vec_blocks), dim3(kVecThreads), 0,
                                c->work, c->n, c->y32.p, y);

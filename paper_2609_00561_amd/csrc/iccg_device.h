@@ -188,6 +188,7 @@ struct iccg_ctx {
     long long flow_sweeps = 0;    // single-launch sweeps since the flags were last cleared
     int num_cu = 0;                 // compute units of the device
     int last_resident = 0;          // workgroups of the last single-launch sweep
+    int flow_tail = 0;              // hybrid sweeps: first color of the dataflow part
     std::unordered_map<const void *, int> resident;   // resident workgroups per CU, per kernel
     double last_ms = 0.0;
     int last_iters = 0;

@@ -145,19 +145,28 @@ def test_poisson128_solve(poisson):
     assert np.allclose(hist[:11], ref.history[:11], rtol=1e-6, atol=0)
 
 
-def test_poisson128_single_launch_identical(poisson):
-    """The persistent single-launch sweep at full size: bit-identical to the
-    per-color launches."""
+@pytest.mark.parametrize("mode", ["single", "hybrid"])
+def test_poisson128_dataflow_sweeps_identical(poisson, mode):
+    """The persistent single-launch sweep and the hybrid (per-color launches
+    for the large colors, one dataflow launch for the small ones) at full
+    size: bit-identical to the per-color launches, for the IC application
+    and for a whole solve."""
     A, b, o, Ap, lval, ctx = poisson
     rp, cl, vl = Ap.rowptr, Ap.col, Ap.val
     r = np.random.default_rng(13).standard_normal(A.n)
     z1 = torch.zeros(A.n, dtype=torch.float64, device="cuda")
     ctx.ic_apply(_dev(r), z1)
-    with iccg.Context(rp, cl, vl, o.block_ptr, o.color_ptr, sweep_launch="single") as c2:
+    bp = _dev(b[np.asarray(o.perm)])
+    x1 = torch.zeros(A.n, dtype=torch.float64, device="cuda")
+    r1 = ctx.solve(bp, x1, tol=1e-8)
+    with iccg.Context(rp, cl, vl, o.block_ptr, o.color_ptr, sweep_launch=mode) as c2:
         c2.ic0_factor()
         z2 = torch.zeros_like(z1)
         c2.ic_apply(_dev(r), z2)
         assert np.array_equal(_host(z1), _host(z2))
+        x2 = torch.zeros_like(x1)
+        r2 = c2.solve(bp, x2, tol=1e-8)
+        assert r2["iters"] == r1["iters"] and np.array_equal(_host(x1), _host(x2))
 
 
 @pytest.fixture(scope="module")

@@ -347,12 +347,13 @@ def test_single_launch_sweep_identical_to_per_color(case, precision):
     through the XCD's L2 inside a region and written through across regions)
     computes the same per-row terms as one launch per color: outputs and
     solves are bit-identical.  Small persistent grids (8 and 64 workgroups)
-    make every workgroup run many tasks in sequence."""
+    make every workgroup run many tasks in sequence; the hybrid mode runs
+    the small colors as one dataflow launch."""
     cs = _case(*case)
     Ap = cs[4]
     r = np.random.default_rng(8).standard_normal(Ap.n)
     outs, sols = [], []
-    for mode, grid in (("per_color", 0), ("single", 0), ("single", 8), ("single", 64)):
+    for mode, grid in (("per_color", 0), ("single", 0), ("single", 8), ("single", 64), ("hybrid", 0)):
         with _ctx(cs, sweep_launch=mode, sweep_grid=grid, precision=precision) as ctx:
             zd = torch.zeros(Ap.n, dtype=torch.float64, device="cuda")
             for _ in range(3):                      # repeated launches reuse the epoch flags
