@@ -431,6 +431,8 @@ enum SweepMode : int { SW_APPLY = 0, SW_CG_FWD = 1, SW_DOT_BWD = 2 };
 
 // Tasks (wavefronts) per workgroup of a per-color sweep launch.
 constexpr int kSweepWaves = 1;
+// Launches of at least this many tasks read the schedule non-temporally.
+constexpr int kStreamTasks = 1024;
 // Hybrid sweeps run the small trailing colors, up to this many tasks in all,
 // as one dataflow launch (measured on 128^3: 700 beats 100 and 2200).
 constexpr int kFlowTailTasks = 700;
@@ -514,7 +516,7 @@ __device__ __forceinline__ void sweep_chunk(const Chunk &ch, const uint32_t *__r
                                             const TIn *__restrict__ in, TOut *__restrict__ out,
                                             const CgArgs &cg, double alpha, F *ys, double &dacc,
                                             const Wait &wait, const Mem &mem, F &y_out,
-                                            uint32_t &m_out) {
+                                            uint32_t &m_out, bool stream) {
     const int t = static_cast<int>(threadIdx.x) & (kChunkRows - 1);
     const int nr = ch.shape & 0xffff, W = ch.shape >> 16;
     const bool active = t < nr;
@@ -528,17 +530,29 @@ __device__ __forceinline__ void sweep_chunk(const Chunk &ch, const uint32_t *__r
     // the first dependency a lane waits for, ahead of the chunk's loads
     const int pre = wait.pre();
     if (active) {
-        // every independent load of the chunk first, so they overlap; the
-        // schedule streams through once (non-temporal: it should not push the
-        // gathered values out of L2)
+        // every independent load of the chunk first, so they overlap.  A large
+        // launch streams its schedule through once (non-temporal: it should
+        // not push the gathered values out of L2); a small one reads it
+        // normally, so it can stay cached between sweeps.
+        if (stream) {
 #pragma unroll
-        for (int k = 0; k < KMAX; ++k)
-            if (k < W) {
-                vv[k] = __builtin_nontemporal_load(sval + base + k * nr);
-                cc[k] = __builtin_nontemporal_load(scol + base + k * nr);
-            }
-        m = __builtin_nontemporal_load(meta + i);
-        dinv = __builtin_nontemporal_load(inv + i);
+            for (int k = 0; k < KMAX; ++k)
+                if (k < W) {
+                    vv[k] = __builtin_nontemporal_load(sval + base + k * nr);
+                    cc[k] = __builtin_nontemporal_load(scol + base + k * nr);
+                }
+            m = __builtin_nontemporal_load(meta + i);
+            dinv = __builtin_nontemporal_load(inv + i);
+        } else {
+#pragma unroll
+            for (int k = 0; k < KMAX; ++k)
+                if (k < W) {
+                    vv[k] = sval[base + k * nr];
+                    cc[k] = scol[base + k * nr];
+                }
+            m = meta[i];
+            dinv = inv[i];
+        }
         if (MODE == SW_CG_FWD) {
             const double ri = cg.r[i] - alpha * cg.q[i];
             cg.r[i] = ri;
@@ -629,8 +643,9 @@ __global__ __launch_bounds__(64 * kSweepWaves) void k_sweep(const TaskRec *__res
     F yv;
     uint32_t m;
     const TaskRec tr = tasks[task];
+    const bool stream = ntasks_color >= kStreamTasks;
     sweep_chunk<F, FWD, KMAX, MODE, TIn, TOut>(tr.first, meta, scol, sval, inv, in, out, cg, alpha,
-                                               ys, dacc, NoWait(), PlainMem(), yv, m);
+                                               ys, dacc, NoWait(), PlainMem(), yv, m, stream);
     const int nchunks = tr.c1 - tr.c0;
     for (int q = 1; q < nchunks; ++q) {
         // later chunks of this task read earlier chunks' results from memory:
@@ -640,7 +655,7 @@ __global__ __launch_bounds__(64 * kSweepWaves) void k_sweep(const TaskRec *__res
         __builtin_amdgcn_wave_barrier();
         const Chunk ch = chunks[FWD ? tr.c0 + q : tr.c1 - 1 - q];
         sweep_chunk<F, FWD, KMAX, MODE, TIn, TOut>(ch, meta, scol, sval, inv, in, out, cg, alpha,
-                                                   ys, dacc, NoWait(), PlainMem(), yv, m);
+                                                   ys, dacc, NoWait(), PlainMem(), yv, m, stream);
     }
     if (MODE != SW_APPLY) {
         const double tsum = wave_sum(dacc);
@@ -757,6 +772,7 @@ __global__ __launch_bounds__(64) void k_sweep_flow(const TaskRec *__restrict__ t
     const int word = (epoch << 4) | xcc;
     const __amdgpu_buffer_rsrc_t rs_out = make_rsrc(out, static_cast<long long>(n) * sizeof(TOut));
     const __amdgpu_buffer_rsrc_t rs_loc = make_rsrc(fa.flag_loc, 4LL * fa.ntasks);
+    const bool stream = fa.pos1 - fa.pos0 >= kStreamTasks;
     for (int pos = fa.pos0 + static_cast<int>(blockIdx.x); pos < fa.pos1; pos += gridDim.x) {
         const int task = fa.wg_task[pos];
         const TaskRec tr = tasks[task];
@@ -768,14 +784,16 @@ __global__ __launch_bounds__(64) void k_sweep_flow(const TaskRec *__restrict__ t
         uint32_t m;
         sweep_chunk<F, FWD, KMAX, MODE, TIn, TOut>(tr.first, meta, scol, sval, inv, in, out, cg,
                                                    alpha, ys, dacc, wait,
-                                                   FlowMem{rs_out, remote, nchunks == 1}, yv, m);
+                                                   FlowMem{rs_out, remote, nchunks == 1}, yv, m,
+                                                   stream);
         for (int q = 1; q < nchunks; ++q) {
             __builtin_amdgcn_s_waitcnt(0);   // this chunk's stores are complete before they are read
             __syncthreads();
             const Chunk ch = chunks[FWD ? tr.c0 + q : tr.c1 - 1 - q];
             sweep_chunk<F, FWD, KMAX, MODE, TIn, TOut>(ch, meta, scol, sval, inv, in, out, cg, alpha,
                                                        ys, dacc, NoWait(),
-                                                       FlowMem{rs_out, remote, q == nchunks - 1}, yv, m);
+                                                       FlowMem{rs_out, remote, q == nchunks - 1}, yv, m,
+                                                       stream);
         }
         if (MODE != SW_APPLY) {
             const double tsum = wave_sum(dacc);
