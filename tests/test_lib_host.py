@@ -107,8 +107,15 @@ def test_order_argument_errors():
 # ---------------------------------------------------------------------------
 # setup validation: runs on the host before any device call
 # ---------------------------------------------------------------------------
-def _raw_setup(rowptr, col, val, block_ptr, color_ptr):
+def _raw_setup(rowptr, col, val, block_ptr, color_ptr, **opts):
     lib = iccg.load()
+    opt = None
+    if opts:
+        opt = iccg._Options()
+        lib.iccg_default_options(ctypes.byref(opt))
+        for k, v in opts.items():
+            setattr(opt, k, v)
+        opt = ctypes.byref(opt)
     rp = np.ascontiguousarray(rowptr, dtype=np.int32)
     cl = np.ascontiguousarray(col, dtype=np.int32)
     vl = np.ascontiguousarray(val, dtype=np.float64)
@@ -116,7 +123,7 @@ def _raw_setup(rowptr, col, val, block_ptr, color_ptr):
     cp = np.ascontiguousarray(color_ptr, dtype=np.int32)
     h = ctypes.c_void_p()
     st = lib.iccg_setup(ctypes.byref(h), rp.size - 1, rp.ctypes.data, cl.ctypes.data, vl.ctypes.data,
-                        bp.size - 1, bp.ctypes.data, cp.size - 1, cp.ctypes.data, None)
+                        bp.size - 1, bp.ctypes.data, cp.size - 1, cp.ctypes.data, opt)
     if st == 0:
         lib.iccg_destroy(h)
     return st
@@ -175,3 +182,18 @@ def test_setup_rejects_nonfinite_values():
     vl = vl.copy()
     vl[7] = np.nan
     assert _raw_setup(rp, cl, vl, o.block_ptr, o.color_ptr) == iccg.ICCG_EINVAL
+
+
+def test_default_options():
+    opt = iccg._Options()
+    iccg.load().iccg_default_options(ctypes.byref(opt))
+    assert (opt.precision, opt.check_every, opt.pack_rows, opt.use_graph) == (iccg.ICCG_FP64, 32, 64, 1)
+    assert (opt.sweep_launch, opt.sweep_grid, opt.flow_tail) == (0, 0, 0)
+
+
+def test_setup_rejects_bad_options():
+    """Option checks come before any device call, so they are host logic."""
+    rp, cl, vl, o = _ordered()
+    for bad in ({"precision": 2}, {"sweep_launch": 3}, {"sweep_launch": -1},
+                {"sweep_grid": -8}, {"flow_tail": -1}):
+        assert _raw_setup(rp, cl, vl, o.block_ptr, o.color_ptr, **bad) == iccg.ICCG_EINVAL, bad
