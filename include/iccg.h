@@ -278,6 +278,22 @@ int  iccg_mpnn_train_step(iccg_mpnn *m, iccg_ctx *c, const double *probes, int n
 int  iccg_mpnn_predict(iccg_mpnn *m, iccg_ctx *c, int bf16, double *lvals);
 void iccg_mpnn_destroy(iccg_mpnn *m);
 
+/* Host only: no device call, no context.  Checks the permuted system and its
+ * ordering exactly as iccg_setup does, builds both substitution schedules
+ * (the chunk packing of Algorithm 1's blocks, Section 3, with pack_rows as in
+ * iccg_options), re-derives their invariants (chunks tile every color; each
+ * row's entries before-chunk first and ascending; every dependency in an
+ * earlier color and at an earlier launch position; every row read across
+ * chunks is waited for; rows read from another region are exported) and
+ * writes 16 counts to out: for the forward, then the backward schedule,
+ * {tasks, chunks, slots, max level depth, max row width, dependencies,
+ * tasks with a dependency in another region, exported rows}.
+ * Returns the iccg_setup error codes, or ICCG_EINVAL naming a violated
+ * invariant.  The caller owns every array. */
+int iccg_schedule_stats(int n, const int *rowptr, const int *col, const double *val,
+                        int nblocks, const int *block_ptr, int ncolors, const int *color_ptr,
+                        int pack_rows, long long *out);
+
 const char *iccg_strerror(int status);
 const char *iccg_last_error(void);
 void iccg_destroy(iccg_ctx *c);

@@ -1709,6 +1709,32 @@ int iccg_residual_history(iccg_ctx *c, double *hist, int cap) {
     return k;
 }
 
+int iccg_schedule_stats(int n, const int *rowptr, const int *col, const double *val, int nblocks,
+                        const int *block_ptr, int ncolors, const int *color_ptr, int pack_rows,
+                        long long *out) {
+    if (!out) return set_error(ICCG_EINVAL, "null output");
+    try {
+        if (pack_rows < 1 || pack_rows > kChunkRows) pack_rows = kChunkRows;
+        HostSetup hs;
+        ICCG_CHECK(validate(n, rowptr, col, val, nblocks, block_ptr, ncolors, color_ptr, pack_rows, hs));
+        int k = 0;
+        for (const SweepPlan *P : {&hs.fwd, &hs.bwd}) {
+            ICCG_CHECK(check_sweep_plan(*P, n, rowptr, col, ncolors, block_ptr, color_ptr));
+            out[k++] = static_cast<long long>(P->task_chunk_ptr.size()) - 1;
+            out[k++] = static_cast<long long>(P->chunks.size());
+            out[k++] = static_cast<long long>(P->slot_col.size());
+            out[k++] = P->max_depth;
+            out[k++] = P->max_width;
+            out[k++] = static_cast<long long>(P->deps.size());
+            out[k++] = P->remote_tasks;
+            out[k++] = P->exported_rows;
+        }
+        return ICCG_OK;
+    } catch (const std::bad_alloc &) {
+        return set_error(ICCG_ENOMEM, "host allocation failed");
+    }
+}
+
 int iccg_get_info(iccg_ctx *c, iccg_info *info) {
     if (!c || !info) return set_error(ICCG_EINVAL, "bad argument");
     std::memset(info, 0, sizeof(*info));

@@ -102,6 +102,8 @@ int build_sell(int n, const int *rowptr, const int *col, const double *val, cons
 
 // Builds both sweep plans from the validated permuted pattern.  tpos[k] is
 // the CSR position of the transpose of entry k.
+int check_sweep_plan(const SweepPlan &plan, int n, const int *rowptr, const int *col, int ncolors,
+                     const int *block_ptr, const int *color_ptr);
 int build_sweep_plan(bool forward, int n, const int *rowptr, const int *col, const int *tpos,
                      int nblocks, const int *block_ptr, int ncolors, const int *color_ptr,
                      int pack_rows, SweepPlan &out);

@@ -204,6 +204,104 @@ int build_sweep_plan(bool forward, int n, const int *rowptr, const int *col, con
     return ICCG_OK;
 }
 
+// Invariants of a finished sweep plan, re-derived independently of how it was
+// built; used by iccg_schedule_stats.  Returns ICCG_OK or an error naming the
+// first violation.
+int check_sweep_plan(const SweepPlan &P, int n, const int *rowptr, const int *col, int ncolors,
+                     const int *block_ptr, const int *color_ptr) {
+    const bool fwd = P.forward;
+    const int ntasks = static_cast<int>(P.task_chunk_ptr.size()) - 1;
+    auto fail = [](const std::string &m) { return set_error(ICCG_EINVAL, "schedule invariant: " + m); };
+    if (static_cast<int>(P.tasks.size()) != ntasks || static_cast<int>(P.wg_task.size()) != ntasks)
+        return fail("task tables disagree in size");
+    // chunks tile each color's rows in order; every row in exactly one chunk
+    std::vector<int> task_of_row(n, -1), color_of_task(ntasks, -1);
+    for (int c = 0; c < ncolors; ++c) {
+        int next = block_ptr[color_ptr[c]];
+        for (int t = P.color_task_ptr[c]; t < P.color_task_ptr[c + 1]; ++t) {
+            color_of_task[t] = c;
+            for (int ch = P.task_chunk_ptr[t]; ch < P.task_chunk_ptr[t + 1]; ++ch) {
+                const Chunk &k = P.chunks[ch];
+                if (k.row0 != next) return fail("chunks do not tile color " + std::to_string(c));
+                const int nr = k.shape & 0xffff;
+                if (nr < 1 || nr > kChunkRows) return fail("chunk row count out of range");
+                for (int i = k.row0; i < k.row0 + nr; ++i) task_of_row[i] = t;
+                next += nr;
+            }
+        }
+        if (next != block_ptr[color_ptr[c + 1]]) return fail("chunks do not cover color " + std::to_string(c));
+    }
+    // slots: every row's triangle entries, before-chunk ones first, each
+    // group ascending; the schedule word's counts agree
+    for (size_t ch = 0; ch < P.chunks.size(); ++ch) {
+        const Chunk &k = P.chunks[ch];
+        const int nr = k.shape & 0xffff, W = k.shape >> 16;
+        for (int t = 0; t < nr; ++t) {
+            const int i = k.row0 + t;
+            const uint32_t m = P.meta[i];
+            const int ne = m & kMetaNextMask, ni = (m >> 16) & 0xff;
+            int cnt = 0;
+            for (int q = rowptr[i]; q < rowptr[i + 1]; ++q)
+                if (fwd ? col[q] < i : col[q] > i) ++cnt;
+            if (ne + ni != cnt || cnt > W) return fail("row " + std::to_string(i) + " entry counts");
+            int prev = -1;
+            for (int s = 0; s < W; ++s) {
+                const int c = P.slot_col[static_cast<long long>(k.off) + static_cast<long long>(s) * nr + t];
+                if (s >= cnt) {
+                    if (c != -1) return fail("padding slot holds an entry");
+                    continue;
+                }
+                const bool inside = c >= k.row0 && c < k.row0 + nr;
+                if (inside != (s >= ne)) return fail("slot group order in row " + std::to_string(i));
+                if (s == ne) prev = -1;
+                if (c <= prev) return fail("slots not ascending in row " + std::to_string(i));
+                prev = c;
+            }
+        }
+    }
+    // launch table: a permutation, colors in processing order; every
+    // dependency an earlier color and an earlier position
+    std::vector<int> pos(ntasks, -1);
+    for (int b = 0; b < ntasks; ++b) {
+        const int t = P.wg_task[b];
+        if (t < 0 || t >= ntasks || pos[t] >= 0) return fail("launch table is not a permutation");
+        pos[t] = b;
+    }
+    for (int t = 0; t < ntasks; ++t) {
+        const int d0 = P.tasks[t].dep0, nd = P.tasks[t].kind_ndeps >> 2;
+        if (d0 != P.dep_ptr[t] || d0 + nd != P.dep_ptr[t + 1]) return fail("task dependency range");
+        for (int d = d0; d < d0 + nd; ++d) {
+            const int u = P.deps[d];
+            if (pos[u] >= pos[t]) return fail("a dependency is not at an earlier position");
+            const bool earlier = fwd ? color_of_task[u] < color_of_task[t] : color_of_task[u] > color_of_task[t];
+            if (!earlier && u != t) return fail("a dependency is not in an earlier color");
+        }
+    }
+    // every row a task reads across chunks comes from its dependencies or its
+    // own earlier chunks; rows read by remote tasks are exported
+    for (int t = 0; t < ntasks; ++t) {
+        const bool remote = P.tasks[t].kind_ndeps & kTaskRemote;
+        const int d0 = P.tasks[t].dep0, nd = P.tasks[t].kind_ndeps >> 2;
+        for (int ch = P.task_chunk_ptr[t]; ch < P.task_chunk_ptr[t + 1]; ++ch) {
+            const Chunk &k = P.chunks[ch];
+            const int nr = k.shape & 0xffff;
+            for (int i = k.row0; i < k.row0 + nr; ++i)
+                for (int q = rowptr[i]; q < rowptr[i + 1]; ++q) {
+                    const int j = col[q];
+                    if (fwd ? j >= i : j <= i) continue;
+                    if (j >= k.row0 && j < k.row0 + nr) continue;
+                    const int u = task_of_row[j];
+                    if (u != t && !std::binary_search(P.deps.begin() + d0, P.deps.begin() + d0 + nd, u))
+                        return fail("row " + std::to_string(i) + " reads a task it does not wait for");
+                    if (remote && !(P.meta[j] & kMetaExport)) return fail("a row read remotely is not exported");
+                    if (remote && !(P.tasks[u].kind_ndeps & kTaskExports))
+                        return fail("a task with exported rows lacks the export kind");
+                }
+        }
+    }
+    return ICCG_OK;
+}
+
 // Launch order of the slices: the k-th eighth of every color's rows goes to
 // the k-th eighth of the launch, so the workgroups that one XCD runs cover the
 // same region of the domain in every color, and the values they gather from

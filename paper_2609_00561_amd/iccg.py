@@ -39,7 +39,8 @@ EXPORTS = [
     "iccg_default_options", "iccg_order_abmc", "iccg_order_leiden", "iccg_permute",
     "iccg_setup", "ic0_factor", "iccg_set_factor", "iccg_restore_ic0", "iccg_get_factor", "ic_apply",
     "ic_forward", "ic_backward", "iccg_spmv", "iccg_dot", "iccg_solve",
-    "iccg_residual_history", "iccg_profile_solve", "iccg_get_info", "iccg_strerror", "iccg_last_error",
+    "iccg_residual_history", "iccg_profile_solve", "iccg_get_info", "iccg_schedule_stats",
+    "iccg_strerror", "iccg_last_error",
     "iccg_destroy", "iccg_mpnn_param_count", "iccg_mpnn_create", "iccg_mpnn_get_params",
     "iccg_mpnn_set_params", "iccg_mpnn_loss_grad", "iccg_mpnn_train_step", "iccg_mpnn_predict",
     "iccg_mpnn_destroy",
@@ -92,6 +93,7 @@ def load():
         "iccg_permute": (i, [i, vp, vp, vp, vp, vp, vp, vp]),
         "iccg_setup": (i, [ctypes.POINTER(vp), i, vp, vp, vp, i, vp, i, vp,
                            ctypes.POINTER(_Options)]),
+        "iccg_schedule_stats": (i, [i, vp, vp, vp, i, vp, i, vp, i, vp]),
         "ic0_factor": (i, [vp, ip]),
         "iccg_set_factor": (i, [vp, vp, ip]),
         "iccg_get_factor": (i, [vp, vp]),
@@ -202,6 +204,24 @@ def iccg_permute(A, perm):
                              prow.ctypes.data, pcol.ctypes.data, pval.ctypes.data)
     _check(st, "iccg_permute")
     return prow, pcol, pval
+
+
+SCHEDULE_FIELDS = ("tasks", "chunks", "slots", "max_depth", "max_width", "deps", "remote_tasks",
+                   "exported_rows")
+
+
+def iccg_schedule_stats(rowptr, col, val, block_ptr, color_ptr, pack_rows: int = 64):
+    """Host-only schedule build and invariant check (no GPU): returns
+    {"forward": {...}, "backward": {...}} with SCHEDULE_FIELDS."""
+    lib = load()
+    rp, cl, vl = _host_i32(rowptr), _host_i32(col), _host_f64(val)
+    bp, cp = _host_i32(block_ptr), _host_i32(color_ptr)
+    out = np.zeros(16, dtype=np.int64)
+    _check(lib.iccg_schedule_stats(rp.size - 1, rp.ctypes.data, cl.ctypes.data, vl.ctypes.data,
+                                   bp.size - 1, bp.ctypes.data, cp.size - 1, cp.ctypes.data,
+                                   int(pack_rows), out.ctypes.data), "iccg_schedule_stats")
+    return {d: dict(zip(SCHEDULE_FIELDS, (int(v) for v in out[8 * k:8 * k + 8])))
+            for k, d in enumerate(("forward", "backward"))}
 
 
 # ---------------------------------------------------------------------------
