@@ -9,6 +9,8 @@
 //   r -= alpha q, ||r||^2 per task,
 //   y = L^{-1} r   (Algorithm 1)              k_sweep<forward>, one launch per color
 //   z = L^{-T} y, (r, z) per task             k_sweep<backward>, one launch per color
+// (or, by option, k_sweep_flow: one dataflow launch for all colors, or for
+// the small ones only)
 //   stopping test on ||r||, beta, rho         k_reduce_rr_beta
 // and after the last iteration x += alpha p   k_axpy_alpha
 // The sweeps give every 64-row chunk of a color one wavefront (one lane per
@@ -663,11 +665,11 @@ __global__ __launch_bounds__(64 * kSweepWaves) void k_sweep(const TaskRec *__res
     }
 }
 
-// Single-launch sweep: every task of every color in one grid.  Workgroup b
-// runs task wg_task[b]; the table lists the tasks in processing order
-// (forward: colors ascending, backward: descending), so every task a
-// workgroup waits for belongs to a workgroup with a smaller index, which the
-// in-order dispatch has already started; that guarantees progress.
+// Dataflow sweep: the tasks of every color (or of a run of colors) in one
+// launch.  The launch table lists the tasks in processing order (forward:
+// colors ascending, backward: descending), and every task a task waits for
+// sits at a smaller table position; how positions map to workgroups and why
+// that guarantees progress is described at k_sweep_flow.
 //
 // Workgroups are dealt to the XCDs round robin, so the workgroups with one
 // value of b mod 8 (one region of the domain in every color) share an XCD
@@ -678,15 +680,14 @@ __global__ __launch_bounds__(64 * kSweepWaves) void k_sweep(const TaskRec *__res
 //             (read coherently by tasks that have a dependency elsewhere).
 // A same-region waiter checks that the producer ran on its own XCD; if the
 // round-robin placement ever failed, the sweep reports an error instead of
-// reading a value that might not be visible.  The epoch is bumped by a
-// one-thread kernel before every launch, so flags are never reset between
-// sweeps.  A wait that exceeds the spin limit sets *err and continues, so
-// every wavefront always exits.
+// reading a value that might not be visible.  The epoch is bumped before
+// every launch (by a one-thread kernel, or in the hybrid mode by a kernel that
+// runs anyway), so flags are never reset between sweeps.  A wait that exceeds
+// the spin limit sets *err and continues, so every wavefront always exits.
 struct FlowArgs {
     const int *epoch;
     int *flag_loc;
     int *flag_rem;
-    const int *dep_ptr;
     const int *deps;
     const int *wg_task;
     int ntasks;
@@ -909,7 +910,6 @@ int launch_flow(iccg_ctx *c, DevSweep &d, const SweepArgs<F> &a, int pos0, int p
     fa.epoch = d.epoch.p;
     fa.flag_loc = d.flag_loc.p;
     fa.flag_rem = d.flag_rem.p;
-    fa.dep_ptr = d.dep_ptr.p;
     fa.deps = d.deps.p;
     fa.wg_task = d.wg_task.p;
     fa.ntasks = d.ntasks;
@@ -1172,7 +1172,6 @@ int upload_sweep(iccg_ctx *c, const SweepPlan &plan, DevSweep &d) {
     d.kmax = plan.max_width <= 4 ? 4 : plan.max_width <= 8 ? 8 : plan.max_width <= 16 ? 16 : 32;
     d.color_task_ptr = plan.color_task_ptr;
     ICCG_CHECK(d.tasks.upload(plan.tasks.data(), plan.tasks.size(), c->work));
-    ICCG_CHECK(d.dep_ptr.upload(plan.dep_ptr.data(), plan.dep_ptr.size(), c->work));
     d.ndeps = static_cast<long long>(plan.deps.size());
     ICCG_CHECK(d.deps.upload(plan.deps.data(), plan.deps.size(), c->work));
     ICCG_CHECK(d.wg_task.upload(plan.wg_task.data(), plan.wg_task.size(), c->work));

@@ -94,7 +94,7 @@ struct DevSweep {
     DevArray<float> sval32;
     // single-launch sweep: sweep number, per-task flags, dependency lists
     DevArray<int> epoch;            // sweep number, bumped before every launch
-    DevArray<int> flag_loc, flag_rem, dep_ptr, deps, wg_task;
+    DevArray<int> flag_loc, flag_rem, deps, wg_task;   // dependency ranges sit in the task records
     long long ndeps = 0;
     long long remote_tasks = 0, exported_rows = 0;
 };
