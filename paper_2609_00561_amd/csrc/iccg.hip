@@ -509,6 +509,23 @@ struct FlowMem {
     }
 };
 
+// Rows stored in slot k of a chunk (see Chunk): a byte of cnt for jagged
+// chunks, every row for padded ones.
+__device__ __forceinline__ int slot_rows(const Chunk &ch, int k, bool jagged, int nr) {
+    return (jagged && k < kJaggedMaxWidth)
+               ? static_cast<int>((ch.cnt[(k >> 2) & 1] >> (8 * (k & 3))) & 0xffu)
+               : nr;
+}
+// v of lane src/4 of the wavefront
+__device__ __forceinline__ double lane_pull(double v, int src) {
+    const int2 p = __builtin_bit_cast(int2, v);
+    return __builtin_bit_cast(double, make_int2(__builtin_amdgcn_ds_bpermute(src, p.x),
+                                                __builtin_amdgcn_ds_bpermute(src, p.y)));
+}
+__device__ __forceinline__ float lane_pull(float v, int src) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute(src, __builtin_bit_cast(int, v)));
+}
+
 template <typename F, bool FWD, int KMAX, int MODE, typename TIn, typename TOut, class Wait = NoWait,
           class Mem = PlainMem>
 __device__ __forceinline__ void sweep_chunk(const Chunk &ch, const uint32_t *__restrict__ meta,
@@ -521,9 +538,12 @@ __device__ __forceinline__ void sweep_chunk(const Chunk &ch, const uint32_t *__r
                                             uint32_t &m_out, bool stream) {
     const int t = static_cast<int>(threadIdx.x) & (kChunkRows - 1);
     const int nr = ch.shape & 0xffff, W = ch.shape >> 16;
+    const bool jagged = W <= kJaggedMaxWidth;
     const bool active = t < nr;
     const int i = ch.row0 + t;
     const int base = ch.off + t;
+    // vv/cc first hold the entries of the row at sorted position t and are
+    // then pulled across to the lanes of their rows (jagged chunks)
     F vv[KMAX];
     int cc[KMAX];
     uint32_t m = 0;
@@ -536,12 +556,19 @@ __device__ __forceinline__ void sweep_chunk(const Chunk &ch, const uint32_t *__r
         // launch streams its schedule through once (non-temporal: it should
         // not push the gathered values out of L2); a small one reads it
         // normally, so it can stay cached between sweeps.
+        int sk = base;
         if (stream) {
 #pragma unroll
             for (int k = 0; k < KMAX; ++k)
                 if (k < W) {
-                    vv[k] = __builtin_nontemporal_load(sval + base + k * nr);
-                    cc[k] = __builtin_nontemporal_load(scol + base + k * nr);
+                    const int rows_k = slot_rows(ch, k, jagged, nr);
+                    vv[k] = F(0);
+                    cc[k] = -1;
+                    if (t < rows_k) {
+                        vv[k] = __builtin_nontemporal_load(sval + sk);
+                        cc[k] = __builtin_nontemporal_load(scol + sk);
+                    }
+                    sk += rows_k;
                 }
             m = __builtin_nontemporal_load(meta + i);
             dinv = __builtin_nontemporal_load(inv + i);
@@ -549,8 +576,14 @@ __device__ __forceinline__ void sweep_chunk(const Chunk &ch, const uint32_t *__r
 #pragma unroll
             for (int k = 0; k < KMAX; ++k)
                 if (k < W) {
-                    vv[k] = sval[base + k * nr];
-                    cc[k] = scol[base + k * nr];
+                    const int rows_k = slot_rows(ch, k, jagged, nr);
+                    vv[k] = F(0);
+                    cc[k] = -1;
+                    if (t < rows_k) {
+                        vv[k] = sval[sk];
+                        cc[k] = scol[sk];
+                    }
+                    sk += rows_k;
                 }
             m = meta[i];
             dinv = inv[i];
@@ -565,9 +598,19 @@ __device__ __forceinline__ void sweep_chunk(const Chunk &ch, const uint32_t *__r
         }
         if (MODE == SW_DOT_BWD) rd = cg.rdot[i];
     }
+    if (active && jagged) {
+        // every row takes its entries from the lane of its sorted position
+        const int src = static_cast<int>((m >> kMetaPosShift) & 63u) * 4;
+#pragma unroll
+        for (int k = 0; k < KMAX; ++k)
+            if (k < W) {
+                vv[k] = lane_pull(vv[k], src);
+                cc[k] = __builtin_amdgcn_ds_bpermute(src, cc[k]);
+            }
+    }
     // values of other tasks are read only after their producers published them
     wait(pre);
-    const int ne = m & kMetaNextMask, ni = (m >> 16) & 0xffu, lev = m >> 24;
+    const int ne = m & kMetaNextMask, ni = (m >> kMetaInnerShift) & 63u, lev = m >> kMetaLevelShift;
     if (active) {
         // all gathers at once (the chunk width is uniform); slots that are not
         // before-chunk terms read a harmless valid address and are discarded

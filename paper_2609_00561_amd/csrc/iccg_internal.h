@@ -18,21 +18,33 @@ constexpr int kChunkRows = 64;
 
 // A chunk is up to 64 consecutive rows of one color that one wavefront
 // substitutes together: either several whole blocks packed side by side or
-// one 64-row piece of a block larger than 64 rows.  Its sweep entries are
-// stored slot-major: entry k of the chunk's row t sits at off + k*nrows + t,
-// so the lanes of a wavefront read consecutive addresses.
+// one 64-row piece of a block larger than 64 rows.  Its rows are given
+// "sorted positions" by decreasing number of entries (ties by row), and its
+// sweep entries are stored slot-major over those positions as jagged
+// diagonals: slot k holds entry k of the cnt_k rows that have more than k
+// entries, the row at sorted position l at off + cnt_0 + ... + cnt_{k-1} + l.
+// So the lanes of a wavefront read consecutive addresses and no padding is
+// stored.  A chunk whose widest row has more than kJaggedMaxWidth entries is
+// padded instead: every row is stored at its own position for each of the
+// width slots (cnt_k = nrows, sorted position = row position, empty slots hold
+// column -1 and value 0).
+constexpr int kJaggedMaxWidth = 8;
 struct Chunk {
     int32_t row0;    // first row (permuted numbering)
     int32_t off;     // first slot of this chunk
     int32_t shape;   // nrows (1..64) | width << 16 (max entries of a row)
     int32_t depth;   // number of intra-chunk levels (>= 1)
+    uint32_t cnt[2]; // jagged chunks: cnt_k in byte k (k < width); else 0
+    int32_t pad[2];
     int nrows() const { return shape & 0xffff; }
     int width() const { return shape >> 16; }
+    bool jagged() const { return width() <= kJaggedMaxWidth; }
+    int slot_rows(int k) const { return jagged() ? static_cast<int>((cnt[k >> 2] >> (8 * (k & 3))) & 0xffu) : nrows(); }
 };
-static_assert(sizeof(Chunk) == 16, "Chunk layout");
+static_assert(sizeof(Chunk) == 32, "Chunk layout");
 
 // One wavefront task: its first chunk in processing order (forward: lowest,
-// backward: highest) inline, so a task starts from a single 32-byte load, the
+// backward: highest) inline, so a task starts from a single 64-byte load, the
 // range [c0, c1) of all its chunks and, for the single-launch sweep, its
 // dependency list deps[dep0, dep0 + ndeps) and kind bits.
 struct TaskRec {
@@ -40,27 +52,36 @@ struct TaskRec {
     int32_t c0, c1;
     int32_t dep0;
     int32_t kind_ndeps;   // kTaskRemote | kTaskExports | ndeps << 2
+    int32_t pad[4];
     int nchunks() const { return c1 - c0; }
 };
-static_assert(sizeof(TaskRec) == 32, "TaskRec layout");
+static_assert(sizeof(TaskRec) == 64, "TaskRec layout");
 
 // Per-row schedule word: number of entries whose value is final before the
-// chunk starts (bits 0..14), the export bit (bit 15, see kMetaExport),
-// number of entries inside the chunk (bits 16..23), intra-chunk level (bits
-// 24..31).  The row's entries are stored "before-chunk first", each group in
-// ascending column order.
-constexpr uint32_t kMetaNextMask = 0x7fffu;
+// chunk starts (bits 0..12), the export bit (bit 13, see kMetaExport), the
+// row's sorted position in its chunk (bits 14..19), number of entries inside
+// the chunk (bits 20..25), intra-chunk level (bits 26..31).  The row's entries
+// are stored "before-chunk first", each group in ascending column order.
+constexpr uint32_t kMetaNextMask = 0x1fffu;
 // Single-launch sweep: the row is read by a task of another region (or by a
 // task that reads through device-coherent loads), so its value is also
 // written through to memory.
-constexpr uint32_t kMetaExport = 0x8000u;
+constexpr uint32_t kMetaExport = 0x2000u;
+constexpr int kMetaPosShift = 14;
+constexpr int kMetaInnerShift = 20;
+constexpr int kMetaLevelShift = 26;
 // TaskRec.kind bits of the single-launch sweep.
 constexpr int kTaskRemote = 1;   // some dependency is in another region
 constexpr int kTaskExports = 2;  // some row of the task has kMetaExport
-inline uint32_t pack_meta(int n_ext, int n_int, int level) {
-    return static_cast<uint32_t>(n_ext) | (static_cast<uint32_t>(n_int) << 16) |
-           (static_cast<uint32_t>(level) << 24);
+inline uint32_t pack_meta(int n_ext, int n_int, int level, int pos) {
+    return static_cast<uint32_t>(n_ext) | (static_cast<uint32_t>(pos) << kMetaPosShift) |
+           (static_cast<uint32_t>(n_int) << kMetaInnerShift) |
+           (static_cast<uint32_t>(level) << kMetaLevelShift);
 }
+inline int meta_next(uint32_t m) { return static_cast<int>(m & kMetaNextMask); }
+inline int meta_pos(uint32_t m) { return static_cast<int>((m >> kMetaPosShift) & 63u); }
+inline int meta_inner(uint32_t m) { return static_cast<int>((m >> kMetaInnerShift) & 63u); }
+inline int meta_level(uint32_t m) { return static_cast<int>(m >> kMetaLevelShift); }
 
 // One sweep direction.  Forward: row i uses L_ij, j < i; chunks of a task run
 // in ascending order, colors ascending.  Backward: row i uses (L^T)_ij = L_ji,
@@ -72,7 +93,7 @@ struct SweepPlan {
     std::vector<TaskRec> tasks;        // ntasks
     std::vector<Chunk> chunks;
     std::vector<uint32_t> meta;        // n
-    std::vector<int> slot_col;         // column per slot, -1 for padding
+    std::vector<int> slot_col;         // column per slot, -1 for padding (see Chunk)
     std::vector<int> slot_src;         // CSR position of the factor value, -1 for padding
     int max_depth = 0;
     int max_width = 0;

@@ -65,7 +65,7 @@ int build_sweep_plan(bool forward, int n, const int *rowptr, const int *col, con
     // 2. per chunk: classify entries, levels, slot layout
     long long nslots = 0;
     RowEntries rows[kChunkRows];
-    int level[kChunkRows];
+    int level[kChunkRows], wid[kChunkRows], sorted[kChunkRows], pos[kChunkRows];
     for (const auto &cr : chunk_rows) {
         const int r0 = cr.first, r1 = cr.second, nr = r1 - r0;
         int width = 0, depth = 0;
@@ -88,35 +88,53 @@ int build_sweep_plan(bool forward, int n, const int *rowptr, const int *col, con
                 }
             }
             level[t] = lev;
-            if (re.ext.size() > kMetaNextMask) return set_error(ICCG_EINVAL, "a row has more than 32767 off-diagonal entries in one triangle");
-            width = std::max(width, static_cast<int>(re.ext.size() + re.inn.size()));
+            if (re.ext.size() > kMetaNextMask)
+                return set_error(ICCG_EINVAL, "a row has more than 8191 off-diagonal entries in one triangle");
+            wid[t] = static_cast<int>(re.ext.size() + re.inn.size());
+            width = std::max(width, wid[t]);
             depth = std::max(depth, lev + 1);
-            out.meta[i] = pack_meta(static_cast<int>(re.ext.size()), static_cast<int>(re.inn.size()), lev);
         }
-        if (nslots + static_cast<long long>(width) * nr >= (1LL << 31))
-            return set_error(ICCG_EINVAL, "substitution schedule exceeds 2^31 slots");
-        Chunk ch;
+        if (width > 0x7fff) return set_error(ICCG_EINVAL, "a row has more than 32767 entries in one triangle");
+        Chunk ch{};
         ch.row0 = r0;
         ch.off = static_cast<int32_t>(nslots);
-        if (width > 0x7fff) return set_error(ICCG_EINVAL, "a row has more than 32767 entries in one triangle");
         ch.shape = nr | (width << 16);
         ch.depth = depth;
+        // sorted positions and the rows of each slot (see Chunk)
+        for (int t = 0; t < nr; ++t) sorted[t] = t;
+        if (ch.jagged())
+            std::stable_sort(sorted, sorted + nr, [&](int a, int b) { return wid[a] > wid[b]; });
+        for (int l = 0; l < nr; ++l) pos[sorted[l]] = l;
+        std::vector<long long> first(width + 1, 0);
+        for (int k = 0; k < width; ++k) {
+            int cnt = nr;
+            if (ch.jagged()) {
+                cnt = 0;
+                for (int t = 0; t < nr; ++t) cnt += wid[t] > k;
+                ch.cnt[k >> 2] |= static_cast<uint32_t>(cnt) << (8 * (k & 3));
+            }
+            first[k + 1] = first[k] + cnt;
+        }
+        if (nslots + first[width] >= (1LL << 31))
+            return set_error(ICCG_EINVAL, "substitution schedule exceeds 2^31 slots");
         out.chunks.push_back(ch);
         out.max_depth = std::max(out.max_depth, depth);
         out.max_width = std::max(out.max_width, width);
-        out.slot_col.resize(nslots + static_cast<long long>(width) * nr, -1);
-        out.slot_src.resize(nslots + static_cast<long long>(width) * nr, -1);
+        out.slot_col.resize(nslots + first[width], -1);
+        out.slot_src.resize(nslots + first[width], -1);
         for (int t = 0; t < nr; ++t) {
+            out.meta[r0 + t] = pack_meta(static_cast<int>(rows[t].ext.size()),
+                                         static_cast<int>(rows[t].inn.size()), level[t], pos[t]);
             int k = 0;
             for (const auto *grp : {&rows[t].ext, &rows[t].inn})
-                for (int pos : *grp) {
-                    const long long slot = nslots + static_cast<long long>(k) * nr + t;
-                    out.slot_col[slot] = col[pos];
-                    out.slot_src[slot] = forward ? pos : tpos[pos];
+                for (int q : *grp) {
+                    const long long slot = nslots + first[k] + pos[t];
+                    out.slot_col[slot] = col[q];
+                    out.slot_src[slot] = forward ? q : tpos[q];
                     ++k;
                 }
         }
-        nslots += static_cast<long long>(width) * nr;
+        nslots += first[width];
     }
     const int ntasks = static_cast<int>(out.task_chunk_ptr.size()) - 1;
     // dependency lists: the tasks owning the before-chunk terms of a task's rows
@@ -223,7 +241,7 @@ int check_sweep_plan(const SweepPlan &P, int n, const int *rowptr, const int *co
             for (int ch = P.task_chunk_ptr[t]; ch < P.task_chunk_ptr[t + 1]; ++ch) {
                 const Chunk &k = P.chunks[ch];
                 if (k.row0 != next) return fail("chunks do not tile color " + std::to_string(c));
-                const int nr = k.shape & 0xffff;
+                const int nr = k.nrows();
                 if (nr < 1 || nr > kChunkRows) return fail("chunk row count out of range");
                 for (int i = k.row0; i < k.row0 + nr; ++i) task_of_row[i] = t;
                 next += nr;
@@ -231,23 +249,36 @@ int check_sweep_plan(const SweepPlan &P, int n, const int *rowptr, const int *co
         }
         if (next != block_ptr[color_ptr[c + 1]]) return fail("chunks do not cover color " + std::to_string(c));
     }
-    // slots: every row's triangle entries, before-chunk ones first, each
-    // group ascending; the schedule word's counts agree
+    // slots: chunks contiguous; sorted positions a permutation ordered by
+    // decreasing entry count (identity for padded chunks); every row's
+    // triangle entries, before-chunk ones first, each group ascending; the
+    // schedule word's counts agree
+    long long next_slot = 0;
     for (size_t ch = 0; ch < P.chunks.size(); ++ch) {
         const Chunk &k = P.chunks[ch];
-        const int nr = k.shape & 0xffff, W = k.shape >> 16;
+        const int nr = k.nrows(), W = k.width();
+        if (k.off != next_slot) return fail("chunk slots are not contiguous");
+        if (!k.jagged() && (k.cnt[0] | k.cnt[1])) return fail("padded chunk with slot counts");
+        std::vector<int> cnt(nr), at(nr, -1);
+        std::vector<long long> first(W + 1, 0);
+        for (int s = 0; s < W; ++s) first[s + 1] = first[s] + k.slot_rows(s);
         for (int t = 0; t < nr; ++t) {
             const int i = k.row0 + t;
             const uint32_t m = P.meta[i];
-            const int ne = m & kMetaNextMask, ni = (m >> 16) & 0xff;
-            int cnt = 0;
+            const int ne = meta_next(m), ni = meta_inner(m), l = meta_pos(m);
+            if (l >= nr || at[l] >= 0) return fail("sorted positions are not a permutation");
+            at[l] = t;
+            if (!k.jagged() && l != t) return fail("padded chunk with moved rows");
             for (int q = rowptr[i]; q < rowptr[i + 1]; ++q)
-                if (fwd ? col[q] < i : col[q] > i) ++cnt;
-            if (ne + ni != cnt || cnt > W) return fail("row " + std::to_string(i) + " entry counts");
+                if (fwd ? col[q] < i : col[q] > i) ++cnt[t];
+            if (ne + ni != cnt[t] || cnt[t] > W) return fail("row " + std::to_string(i) + " entry counts");
             int prev = -1;
             for (int s = 0; s < W; ++s) {
-                const int c = P.slot_col[static_cast<long long>(k.off) + static_cast<long long>(s) * nr + t];
-                if (s >= cnt) {
+                if ((l < k.slot_rows(s)) != (s < cnt[t] || !k.jagged()))
+                    return fail("slot counts disagree with row " + std::to_string(i));
+                if (l >= k.slot_rows(s)) continue;
+                const int c = P.slot_col[k.off + first[s] + l];
+                if (s >= cnt[t]) {
                     if (c != -1) return fail("padding slot holds an entry");
                     continue;
                 }
@@ -258,7 +289,11 @@ int check_sweep_plan(const SweepPlan &P, int n, const int *rowptr, const int *co
                 prev = c;
             }
         }
+        for (int l = 1; l < nr; ++l)
+            if (k.jagged() && cnt[at[l]] > cnt[at[l - 1]]) return fail("sorted positions out of order");
+        next_slot += first[W];
     }
+    if (next_slot != static_cast<long long>(P.slot_col.size())) return fail("slot array size");
     // launch table: a permutation, colors in processing order; every
     // dependency an earlier color and an earlier position
     std::vector<int> pos(ntasks, -1);
