@@ -284,10 +284,12 @@ void iccg_mpnn_destroy(iccg_mpnn *m);
  * iccg_options), re-derives their invariants (chunks tile every color; each
  * row's entries before-chunk first and ascending; every dependency in an
  * earlier color and at an earlier launch position; every row read across
- * chunks is waited for; rows read from another region are exported) and
- * writes 16 counts to out: for the forward, then the backward schedule,
- * {tasks, chunks, slots, max level depth, max row width, dependencies,
- * tasks with a dependency in another region, exported rows}.
+ * chunks is waited for; rows read from another region are exported; slot
+ * layout jagged or padded as the chunk's width requires) and writes 18 counts
+ * to out: for the forward, then the backward schedule, {tasks, chunks, slots,
+ * max level depth, max row width, dependencies, tasks with a dependency in
+ * another region, exported rows, padded chunks (widest row above 8 entries,
+ * every row stored at the chunk's width)}.
  * Returns the iccg_setup error codes, or ICCG_EINVAL naming a violated
  * invariant.  The caller owns every array. */
 int iccg_schedule_stats(int n, const int *rowptr, const int *col, const double *val,

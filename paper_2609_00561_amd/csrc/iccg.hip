@@ -1770,6 +1770,8 @@ int iccg_schedule_stats(int n, const int *rowptr, const int *col, const double *
             out[k++] = static_cast<long long>(P->deps.size());
             out[k++] = P->remote_tasks;
             out[k++] = P->exported_rows;
+            out[k++] = std::count_if(P->chunks.begin(), P->chunks.end(),
+                                     [](const Chunk &ch) { return !ch.jagged(); });
         }
         return ICCG_OK;
     } catch (const std::bad_alloc &) {

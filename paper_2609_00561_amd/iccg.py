@@ -207,7 +207,7 @@ def iccg_permute(A, perm):
 
 
 SCHEDULE_FIELDS = ("tasks", "chunks", "slots", "max_depth", "max_width", "deps", "remote_tasks",
-                   "exported_rows")
+                   "exported_rows", "padded_chunks")
 
 
 def iccg_schedule_stats(rowptr, col, val, block_ptr, color_ptr, pack_rows: int = 64):
@@ -216,11 +216,12 @@ def iccg_schedule_stats(rowptr, col, val, block_ptr, color_ptr, pack_rows: int =
     lib = load()
     rp, cl, vl = _host_i32(rowptr), _host_i32(col), _host_f64(val)
     bp, cp = _host_i32(block_ptr), _host_i32(color_ptr)
-    out = np.zeros(16, dtype=np.int64)
+    nf = len(SCHEDULE_FIELDS)
+    out = np.zeros(2 * nf, dtype=np.int64)
     _check(lib.iccg_schedule_stats(rp.size - 1, rp.ctypes.data, cl.ctypes.data, vl.ctypes.data,
                                    bp.size - 1, bp.ctypes.data, cp.size - 1, cp.ctypes.data,
                                    int(pack_rows), out.ctypes.data), "iccg_schedule_stats")
-    return {d: dict(zip(SCHEDULE_FIELDS, (int(v) for v in out[8 * k:8 * k + 8])))
+    return {d: dict(zip(SCHEDULE_FIELDS, (int(v) for v in out[nf * k:nf * k + nf])))
             for k, d in enumerate(("forward", "backward"))}
 
 

@@ -284,6 +284,14 @@ def _w_stencil27(m):
     return make
 
 
+def _w_randspd(n, density):
+    def make(seed):
+        rng = np.random.default_rng(seed)
+        A = random_spd_mmatrix(n, density, rng)
+        return A, uniform_rhs(A.n, rng)
+    return make
+
+
 def _w_learned(m):
     def make(seed):
         rng = np.random.default_rng(seed)
@@ -305,6 +313,7 @@ WORKLOADS = {
     "stencil27_96": _w_stencil27(96),     # n=884,736
     "stencil27_32": _w_stencil27(32),
     "stencil27_12": _w_stencil27(12),
+    "randspd_2k": _w_randspd(2000, 0.03),  # about 60 neighbours per row
     "lognormal7_32": _w_learned(32),      # learned-form training matrices
     "lognormal7_64": _w_learned(64),
     "lognormal7_128": _w_learned(128),

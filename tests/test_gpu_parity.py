@@ -84,6 +84,7 @@ CASES = [
     ("knn13_20k", "leiden", ("cpm", 0.05)),
     ("stencil27_12", "abmc", 64),
     ("poisson7_32", "abmc", 16),
+    ("randspd_2k", "abmc", 16),    # rows of 40-80 entries: padded chunks, entries beyond KMAX
 ]
 
 
@@ -115,7 +116,7 @@ def test_ic_apply_parity(case):
     assert _rel_inf(got, want) <= 1e-12
 
 
-@pytest.mark.parametrize("case", CASES[:6], ids=_ids)
+@pytest.mark.parametrize("case", CASES[:6] + [CASES[9]], ids=_ids)
 def test_forward_backward_parity(case):
     cs = _case(*case)
     Ap, lval = cs[4], cs[5]
@@ -340,7 +341,7 @@ def test_fp32_solve_converges(case):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
-@pytest.mark.parametrize("case", [CASES[1], CASES[3], CASES[6], CASES[7], CASES[8],
+@pytest.mark.parametrize("case", [CASES[1], CASES[3], CASES[6], CASES[7], CASES[8], CASES[9],
                                   ("poisson7_64", "abmc", 16)], ids=_ids)
 def test_single_launch_sweep_identical_to_per_color(case, precision):
     """The single-launch sweep (per-task dependency waits, values passed

@@ -48,7 +48,7 @@ def _replica(rp, cl, bp, cp, forward, pack=64):
     for t, ids in enumerate(task_chunks):
         for ch in ids:
             task_of_row[chunks[ch][0]:chunks[ch][1]] = t
-    slots, max_depth, max_width = 0, 0, 0
+    slots, max_depth, max_width, padded = 0, 0, 0, 0
     for r0, r1 in chunks:
         width, widths, level = 0, 0, {}
         rows = range(r0, r1) if forward else range(r1 - 1, r0 - 1, -1)
@@ -62,6 +62,7 @@ def _replica(rp, cl, bp, cp, forward, pack=64):
                     lev = max(lev, level[j] + 1)
             level[i] = lev
         slots += width * (r1 - r0) if width > 8 else widths
+        padded += width > 8
         max_width = max(max_width, width)
         max_depth = max(max_depth, max(level.values()) + 1)
     rows = np.repeat(np.arange(n), np.diff(rp))
@@ -70,7 +71,8 @@ def _replica(rp, cl, bp, cp, forward, pack=64):
     other = ti != tj
     deps = np.unique(ti[other] * len(task_chunks) + tj[other]).size
     return {"tasks": len(task_chunks), "chunks": len(chunks), "slots": slots,
-            "max_depth": max_depth, "max_width": max_width, "deps": deps}
+            "max_depth": max_depth, "max_width": max_width, "deps": deps,
+            "padded_chunks": padded}
 
 
 CASES = [
@@ -82,6 +84,7 @@ CASES = [
     ("knn13_20k", "leiden", ("cpm", 0.05), 64),
     ("stencil27_12", "abmc", 32, 64),
     ("poisson7_32", "abmc", 16, 32),
+    ("randspd_2k", "abmc", 16, 64),                         # rows of 40-80 entries
 ]
 
 
@@ -98,6 +101,16 @@ def test_schedule_counts_and_invariants(case):
             assert got[d][key] == v, (d, key, got[d][key], v)
         assert got[d]["remote_tasks"] <= got[d]["tasks"]
         assert got[d]["exported_rows"] <= A.n
+    # both slot layouts are exercised: the 7-point and 5-point matrices have
+    # no chunk wider than 8 entries, the others have padded chunks, and the
+    # dense random matrix has rows wider than the 32 entries kept in registers
+    if name.startswith(("poisson7", "laplace2d")):
+        assert got["forward"]["padded_chunks"] == got["backward"]["padded_chunks"] == 0
+    else:
+        assert got["forward"]["padded_chunks"] > 0 and got["backward"]["padded_chunks"] > 0
+    if name.startswith("randspd"):
+        assert got["forward"]["padded_chunks"] < got["forward"]["chunks"]
+        assert got["forward"]["max_width"] > 32
     # the two triangles hold the same number of entries, so only padding
     # can differ between the directions
     nnz_l = (A.nnz - A.n) // 2
