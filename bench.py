@@ -176,6 +176,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=100)
     ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--no-other-matrices", action="store_true",
+                    help="skip the FEM-like kNN and 27-point stencil entries")
     ap.add_argument("--learned-matrices", type=int, default=256)
     ap.add_argument("--learned-epochs", type=int, default=4)
     ap.add_argument("--seed", type=int, default=42)
@@ -184,6 +186,78 @@ def parse():
     ap.add_argument("--traffic-summary", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "CMD_FETCH", "CMD_WRITE"),
                     help="write the traffic summary from two rocprofv3 csv passes (no GPU)")
     return ap.parse_args()
+
+
+def other_matrices(args, dev, iccg, synth, log):
+    """The FEM-like unstructured matrix (13-NN graph Laplacian on 10^6
+    points) under three orderings, and the 27-point stencil on 96^3, each
+    solved in FP64 and, on one ordering, with the FP32 form: solve time,
+    iterations, sweep and SpMV bandwidth of an instrumented solve, and the
+    FP32 solution's distance from the FP64 one."""
+    import torch
+    entries = []
+
+    def solve_entry(A, b, order, label, tblock, precision="fp64", x_ref=None, once=False):
+        # once: a single timed solve and no instrumented one (orderings whose
+        # solve takes seconds)
+        rp, cl, vl = iccg.iccg_permute(A, order.perm)
+        with iccg.Context(rp, cl, vl, order.block_ptr, order.color_ptr, precision=precision) as ctx:
+            ctx.ic0_factor()
+            bd = torch.tensor(b[order.perm], device=dev)
+            xd = torch.zeros(A.n, dtype=torch.float64, device=dev)
+            if not once:
+                ctx.solve(bd, xd, tol=args.tol)
+            times = []
+            for _ in range(1 if once else 2):
+                xd.zero_()
+                torch.cuda.synchronize()
+                ts = time.perf_counter()
+                res = ctx.solve(bd, xd, tol=args.tol)
+                torch.cuda.synchronize()
+                times.append(time.perf_counter() - ts)
+            x = xd.cpu().numpy()
+            info = ctx.info()
+            prof = None if once else ctx.profile_solve(bd, torch.zeros_like(xd), tol=args.tol)
+        nc = info["ncolors"]
+        e = {"matrix": label, "precision": precision, "n": A.n, "nnz": A.nnz,
+             "n_b": order.nblocks, "n_c": nc, "max_block": info["max_block"], "iters": res["iters"],
+             "ms": round(1e3 * float(np.median(times)), 3), "relres_true": res["relres_true"]}
+        if prof is not None:
+            fwd_ms = prof["fwd_ms"] / max(prof["fwd_launches"], 1)
+            spmv_ms = prof["spmv_ms"] / max(prof["spmv_launches"], 1)
+            e["forward_sweep_GBps"] = round(((info["sweep_bytes"] + 16.0 * A.n) / nc) / (fwd_ms * 1e-3) / 1e9, 1)
+            e["spmv_GBps"] = round(info["spmv_bytes"] / (spmv_ms * 1e-3) / 1e9, 1)
+        if tblock is not None:
+            e["blocking_s"] = round(tblock, 2)
+        if x_ref is not None:
+            e["x_rel_diff_vs_fp64"] = float(np.linalg.norm(x - x_ref) / np.linalg.norm(x_ref))
+        log(f"[bench] {label} {precision}: {e}")
+        entries.append(e)
+        return x
+
+    A, b = synth.workload("knn13_1m", args.seed)
+    x_abmc = None
+    # Leiden-MD forms a few dozen communities of 10^4 rows, each one task of
+    # hundreds of 64-row chunks in sequence: a solve of seconds
+    for label, make, once in (("knn13_1m ABMC s=32", lambda: iccg.iccg_order_abmc(A, 32), False),
+                              ("knn13_1m Leiden-CPM gamma=0.05",
+                               lambda: iccg.iccg_order_leiden(A, "cpm", 0.05), False),
+                              ("knn13_1m Leiden-MD gamma=1",
+                               lambda: iccg.iccg_order_leiden(A, "modularity", 1.0), True)):
+        tb = time.time()
+        order = make()
+        tb = time.time() - tb
+        x = solve_entry(A, b, order, label, tb, once=once)
+        if x_abmc is None:
+            x_abmc = x
+            solve_entry(A, b, order, label, None, precision="fp32", x_ref=x_abmc)
+    A, b = synth.workload("stencil27_96", args.seed)
+    tb = time.time()
+    order = iccg.iccg_order_abmc(A, 32)
+    tb = time.time() - tb
+    x64 = solve_entry(A, b, order, "stencil27_96 ABMC s=32", tb)
+    solve_entry(A, b, order, "stencil27_96 ABMC s=32", None, precision="fp32", x_ref=x64)
+    return entries
 
 
 def main():
@@ -359,6 +433,9 @@ def main():
                        "speedup_vs_fp64": round(ms_per_step / (1e3 * float(np.median(times32))), 3)}
         ctx32.close()
         log(f"[bench] FP32 form: {out['fp32']}")
+
+    if not args.no_other_matrices:
+        out["other_matrices"] = other_matrices(args, dev, iccg, synth, log)
 
     if not args.no_learned:
         from paper_2609_00561_amd import learned
