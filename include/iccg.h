@@ -73,7 +73,13 @@ typedef struct {
                            one launch per large color, and the small last colors
                            of the forward sweep (first of the backward sweep) in
                            one such dataflow launch.  Same arithmetic and
-                           bit-identical results in all three.                   */
+                           bit-identical results in all three.  Modes 1 and 2
+                           need every workgroup of the dataflow launch resident
+                           and the runtime's round-robin XCD placement; a failed
+                           placement check or a dependency wait beyond its spin
+                           limit makes the call return ICCG_EHIP, naming the
+                           cause (iccg_last_error), and its output is invalid.
+                           Every wave still exits.                               */
     int   sweep_grid;   /* single-launch sweep: its workgroups, all of which must
                            be resident at once (0 = 8 per compute unit; otherwise
                            this many, bounded by the resident capacity and rounded
