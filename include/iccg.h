@@ -139,7 +139,8 @@ int iccg_permute(int n, const int *rowptr, const int *col, const double *val, co
  * (ICCG_EPATTERN); block_ptr monotone from 0 to n, color_ptr monotone from 0
  * to nblocks, and no stored a'_ij joining two different blocks of one color
  * (ICCG_EBADORDER).  Builds the per-wavefront substitution schedules for both
- * sweeps.  opt may be NULL (defaults).  *out is NULL on failure.
+ * sweeps.  opt may be NULL (defaults).  *out is NULL on failure.  An empty
+ * matrix (n < 1) is rejected with ICCG_EINVAL; non-finite values likewise.
  */
 int iccg_setup(iccg_ctx **out, int n, const int *rowptr, const int *col, const double *val,
                int nblocks, const int *block_ptr, int ncolors, const int *color_ptr,

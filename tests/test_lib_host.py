@@ -184,6 +184,31 @@ def test_setup_rejects_nonfinite_values():
     assert _raw_setup(rp, cl, vl, o.block_ptr, o.color_ptr) == iccg.ICCG_EINVAL
 
 
+def _empty():
+    class Empty:
+        n, nnz = 0, 0
+        rowptr = np.array([0], dtype=np.int32)
+        col = np.array([], dtype=np.int32)
+        val = np.array([], dtype=np.float64)
+    return Empty()
+
+
+def test_empty_matrix():
+    """n = 0: the orderings and the permutation return the empty ordering;
+    setup rejects it (there is nothing to solve)."""
+    A = _empty()
+    for o in (iccg.iccg_order_abmc(A, 16), iccg.iccg_order_leiden(A, "cpm", 0.05),
+              iccg.iccg_order_leiden(A, "modularity", 1.0)):
+        assert (o.nblocks, o.ncolors, np.asarray(o.perm).size) == (0, 0, 0)
+        assert list(o.block_ptr) == [0] and list(o.color_ptr) == [0]
+    assert _same(oracle.order_abmc(A, 16), iccg.iccg_order_abmc(A, 16))
+    assert _same(oracle.order_leiden(A, "cpm", 0.05), iccg.iccg_order_leiden(A, "cpm", 0.05))
+    rp, cl, vl = iccg.iccg_permute(A, np.array([], dtype=np.int32))
+    assert list(rp) == [0] and np.asarray(cl).size == 0 and np.asarray(vl).size == 0
+    assert _raw_setup(A.rowptr, A.col, A.val, [0], [0]) == iccg.ICCG_EINVAL
+    assert b"n >= 1" in iccg.load().iccg_last_error()
+
+
 def test_default_options():
     opt = iccg._Options()
     iccg.load().iccg_default_options(ctypes.byref(opt))
