@@ -85,6 +85,7 @@ CASES = [
     ("stencil27_12", "abmc", 64),
     ("poisson7_32", "abmc", 16),
     ("randspd_2k", "abmc", 16),    # rows of 40-80 entries: padded chunks, entries beyond KMAX
+    ("poisson7_16", "abmc", 1),    # node-level multicoloring: one row per block, depth-1 chunks
 ]
 
 
