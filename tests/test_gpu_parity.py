@@ -350,13 +350,16 @@ def test_single_launch_sweep_identical_to_per_color(case, precision):
     computes the same per-row terms as one launch per color: outputs and
     solves are bit-identical.  Small persistent grids (8 and 64 workgroups)
     make every workgroup run many tasks in sequence; the hybrid mode runs
-    the small colors as one dataflow launch."""
+    the small colors as one dataflow launch, here with three tail sizes."""
     cs = _case(*case)
     Ap = cs[4]
     r = np.random.default_rng(8).standard_normal(Ap.n)
     outs, sols = [], []
-    for mode, grid in (("per_color", 0), ("single", 0), ("single", 8), ("single", 64), ("hybrid", 0)):
-        with _ctx(cs, sweep_launch=mode, sweep_grid=grid, precision=precision) as ctx:
+    # hybrid tails: the default (700 tasks), 1 task (only single-task colors in
+    # the dataflow launch, if any) and unbounded (every color in it)
+    for mode, grid, tail in (("per_color", 0, 0), ("single", 0, 0), ("single", 8, 0), ("single", 64, 0),
+                             ("hybrid", 0, 0), ("hybrid", 0, 1), ("hybrid", 0, 1 << 30)):
+        with _ctx(cs, sweep_launch=mode, sweep_grid=grid, flow_tail=tail, precision=precision) as ctx:
             zd = torch.zeros(Ap.n, dtype=torch.float64, device="cuda")
             for _ in range(3):                      # repeated launches reuse the epoch flags
                 ctx.ic_apply(_dev(r), zd)
