@@ -178,6 +178,9 @@ def parse():
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--no-other-matrices", action="store_true",
                     help="skip the FEM-like kNN and 27-point stencil entries")
+    ap.add_argument("--leiden-md-gammas", default="",
+                    help="extra Leiden-MD resolutions for the kNN graph, e.g. 2,4,8,16 "
+                         "(the resolution sensitivity study; each solve takes seconds)")
     ap.add_argument("--learned-matrices", type=int, default=256)
     ap.add_argument("--learned-epochs", type=int, default=4)
     ap.add_argument("--seed", type=int, default=42)
@@ -243,7 +246,10 @@ def other_matrices(args, dev, iccg, synth, log):
                               ("knn13_1m Leiden-CPM gamma=0.05",
                                lambda: iccg.iccg_order_leiden(A, "cpm", 0.05), False),
                               ("knn13_1m Leiden-MD gamma=1",
-                               lambda: iccg.iccg_order_leiden(A, "modularity", 1.0), True)):
+                               lambda: iccg.iccg_order_leiden(A, "modularity", 1.0), True)) + tuple(
+            (f"knn13_1m Leiden-MD gamma={g:g}",
+             (lambda g=g: iccg.iccg_order_leiden(A, "modularity", g)), True)
+            for g in [float(v) for v in args.leiden_md_gammas.split(",") if v]):
         tb = time.time()
         order = make()
         tb = time.time() - tb
