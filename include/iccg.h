@@ -86,9 +86,16 @@ typedef struct {
                            down to a multiple of 8, at least 8)                  */
     int   flow_tail;    /* hybrid sweeps: at most this many tasks in the dataflow
                            part (0 = 700)                                       */
+    int   wide_blocks;  /* per-color launches: a block of more than 256 rows is
+                           run by a workgroup of 8 wavefronts in pieces of 512
+                           rows, each piece level-scheduled as a whole (1,
+                           default), or by one wavefront in 64-row chunks (0).
+                           The forward sweep is bit-identical either way; the
+                           backward sweep's per-row sums group the entries by
+                           piece instead of by chunk (equal up to rounding).   */
 } iccg_options;
 
-/* Fills *opt with the defaults above (FP64, null stream, 32, 64, 1, 0, 0, 0). */
+/* Fills *opt with the defaults above (FP64, null stream, 32, 64, 1, 0, 0, 0, 1). */
 void iccg_default_options(iccg_options *opt);
 
 /* ------------------------------------------------------------------------ */

@@ -688,6 +688,7 @@ __global__ __launch_bounds__(64 * kSweepWaves) void k_sweep(const TaskRec *__res
     F yv;
     uint32_t m;
     const TaskRec tr = tasks[task];
+    if (tr.wide >= 0) return;   // run by k_sweep_wide
     const bool stream = ntasks_color >= kStreamTasks;
     sweep_chunk<F, FWD, KMAX, MODE, TIn, TOut>(tr.first, meta, scol, sval, inv, in, out, cg, alpha,
                                                ys, dacc, NoWait(), PlainMem(), yv, m, stream);
@@ -705,6 +706,110 @@ __global__ __launch_bounds__(64 * kSweepWaves) void k_sweep(const TaskRec *__res
     if (MODE != SW_APPLY) {
         const double tsum = wave_sum(dacc);
         if ((threadIdx.x & 63) == 0) cg.part[task] = tsum;
+    }
+}
+
+// Wide task (see WidePlan): one block of more than 64 rows, run piece by
+// piece by a workgroup of kWideWaves wavefronts.  Wavefront w takes
+// sub-chunk w of the piece, one lane per row.  Terms from outside the piece
+// are gathered first (earlier pieces of the block were stored by this
+// workgroup before the barrier that ends them); then the piece's levels run
+// with a workgroup barrier after each, the values passing through LDS.
+template <typename F, bool FWD, int KMAX, int MODE, typename TIn, typename TOut>
+__global__ __launch_bounds__(64 * kWideWaves) void k_sweep_wide(
+    const int *__restrict__ wtask, const int *__restrict__ piece_ptr,
+    const WidePiece *__restrict__ pieces, const Chunk *__restrict__ subs,
+    const uint32_t *__restrict__ wmeta, const int *__restrict__ wlev, const int *__restrict__ scol,
+    const F *__restrict__ sval, const F *__restrict__ inv, int w_base, const TIn *__restrict__ in,
+    TOut *__restrict__ out, CgArgs cg) {
+    if (cg.sc && cg.sc->done != DONE_RUNNING) return;
+    __shared__ F ys[kWideRows];
+    const int t = static_cast<int>(threadIdx.x) & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) >> 6);
+    const int w = w_base + static_cast<int>(blockIdx.x);
+    const double alpha = (MODE == SW_CG_FWD) ? cg.sc->alpha : 0.0;
+    double dacc = 0.0;
+    for (int pc = piece_ptr[w]; pc < piece_ptr[w + 1]; ++pc) {
+        const WidePiece P = pieces[pc];
+        int row0 = 0, off = 0, nr = 0, W = 0;
+        if (wave < P.nsub) {
+            const Chunk sc = subs[P.sub0 + wave];
+            row0 = sc.row0;
+            off = sc.off;
+            nr = sc.shape & 0xffff;
+            W = sc.shape >> 16;
+        }
+        const bool active = t < nr;
+        const int i = row0 + t;
+        const int base = off + t;
+        F vv[KMAX];
+        int cc[KMAX];
+        uint32_t m = 0;
+        int lev = 0;
+        F s = F(0), dinv = F(0);
+        double rd = 0.0;
+        if (active) {
+#pragma unroll
+            for (int k = 0; k < KMAX; ++k)
+                if (k < W) {
+                    vv[k] = sval[base + k * nr];
+                    cc[k] = scol[base + k * nr];
+                }
+            m = wmeta[i];
+            lev = wlev[i];
+            dinv = inv[i];
+            if (MODE == SW_CG_FWD) {
+                const double ri = cg.r[i] - alpha * cg.q[i];
+                cg.r[i] = ri;
+                dacc += ri * ri;
+                s = static_cast<F>(ri);
+            } else {
+                s = static_cast<F>(in[i]);
+            }
+            if (MODE == SW_DOT_BWD) rd = cg.rdot[i];
+        }
+        const int ne = static_cast<int>(m & 0xffffu), ni = static_cast<int>(m >> 16);
+        if (active) {
+            // terms from outside the piece, ascending; the padding and the
+            // piece's own slots read a harmless valid address
+            F g[KMAX];
+#pragma unroll
+            for (int k = 0; k < KMAX; ++k)
+                if (k < W) g[k] = static_cast<F>(out[cc[k] < 0 ? 0 : cc[k]]);
+#pragma unroll
+            for (int k = 0; k < KMAX; ++k)
+                if (k < W) s = (k < ne) ? s - vv[k] * g[k] : s;
+            for (int k = KMAX; k < ne; ++k) {
+                const int sl = base + k * nr;
+                s -= sval[sl] * static_cast<F>(out[scol[sl]]);
+            }
+        }
+        for (int L = 0; L < P.depth; ++L) {
+            if (active && lev == L) {
+#pragma unroll
+                for (int k = 0; k < KMAX; ++k)
+                    if (k >= ne && k < ne + ni) s -= vv[k] * ys[cc[k] - P.row0];
+                for (int k = max(KMAX, ne); k < ne + ni; ++k) {
+                    const int sl = base + k * nr;
+                    s -= sval[sl] * ys[scol[sl] - P.row0];
+                }
+                ys[i - P.row0] = s * dinv;
+            }
+            __syncthreads();
+        }
+        if (active) {
+            const F yv = ys[i - P.row0];
+            out[i] = static_cast<TOut>(yv);
+            if (MODE == SW_DOT_BWD) dacc += rd * static_cast<double>(yv);
+        }
+        // the next piece gathers these values from memory
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        __syncthreads();
+    }
+    if (MODE != SW_APPLY) {
+        const double tsum = block_sum<64 * kWideWaves>(dacc);
+        if (threadIdx.x == 0) cg.part[wtask[w]] = tsum;
     }
 }
 
@@ -1015,18 +1120,40 @@ int launch_sweep_t(iccg_ctx *c, const void *in, void *out, const CgArgs &cg) {
     const int tail_tasks = d.color_task_ptr[c->ncolors] - d.color_task_ptr[tail];
 #define SWEEP_ARGS a.tasks, a.chunks, a.meta, a.scol, a.sval, a.inv, t0, t1 - t0, bump, pin, pout, cg
     int launched = 0;
+    // wide tasks (per-color launches only): values and LDS-level pieces of
+    // the blocks of more than 64 rows
+    const DevWide &dw = d.wide;
+    const F *wsval = nullptr;
+    if constexpr (sizeof(F) == 4) wsval = dw.sval32.p; else wsval = dw.sval64.p;
+#define WIDE_ARGS dw.task.p, dw.piece_ptr.p, dw.pieces.p, dw.subs.p, dw.wmeta.p, dw.wlev.p, dw.scol.p, \
+                  wsval, a.inv, w0, pin, pout, cg
     auto per_color = [&](int col, int *bump) -> int {
         const int t0 = d.color_task_ptr[col], t1 = d.color_task_ptr[col + 1];
         if (t1 == t0) return ICCG_OK;
-        ++launched;
-        const dim3 grid((t1 - t0 + kSweepWaves - 1) / kSweepWaves), block(64 * kSweepWaves);
-        switch (d.kmax) {
-            case 4: hipLaunchKernelGGL((k_sweep<F, FWD, 4, MODE, TIn, TOut>), grid, block, 0, c->work, SWEEP_ARGS); break;
-            case 8: hipLaunchKernelGGL((k_sweep<F, FWD, 8, MODE, TIn, TOut>), grid, block, 0, c->work, SWEEP_ARGS); break;
-            case 16: hipLaunchKernelGGL((k_sweep<F, FWD, 16, MODE, TIn, TOut>), grid, block, 0, c->work, SWEEP_ARGS); break;
-            default: hipLaunchKernelGGL((k_sweep<F, FWD, 32, MODE, TIn, TOut>), grid, block, 0, c->work, SWEEP_ARGS); break;
+        const int w0 = dw.nwide > 0 ? dw.color_ptr[col] : 0;
+        const int nw = dw.nwide > 0 ? dw.color_ptr[col + 1] - w0 : 0;
+        if (t1 - t0 > nw || bump) {
+            ++launched;
+            const dim3 grid((t1 - t0 + kSweepWaves - 1) / kSweepWaves), block(64 * kSweepWaves);
+            switch (d.kmax) {
+                case 4: hipLaunchKernelGGL((k_sweep<F, FWD, 4, MODE, TIn, TOut>), grid, block, 0, c->work, SWEEP_ARGS); break;
+                case 8: hipLaunchKernelGGL((k_sweep<F, FWD, 8, MODE, TIn, TOut>), grid, block, 0, c->work, SWEEP_ARGS); break;
+                case 16: hipLaunchKernelGGL((k_sweep<F, FWD, 16, MODE, TIn, TOut>), grid, block, 0, c->work, SWEEP_ARGS); break;
+                default: hipLaunchKernelGGL((k_sweep<F, FWD, 32, MODE, TIn, TOut>), grid, block, 0, c->work, SWEEP_ARGS); break;
+            }
+            HIP_CHECK(hipGetLastError());
         }
-        HIP_CHECK(hipGetLastError());
+        if (nw > 0) {
+            ++launched;
+            const dim3 grid(nw), block(64 * kWideWaves);
+            switch (d.kmax) {
+                case 4: hipLaunchKernelGGL((k_sweep_wide<F, FWD, 4, MODE, TIn, TOut>), grid, block, 0, c->work, WIDE_ARGS); break;
+                case 8: hipLaunchKernelGGL((k_sweep_wide<F, FWD, 8, MODE, TIn, TOut>), grid, block, 0, c->work, WIDE_ARGS); break;
+                case 16: hipLaunchKernelGGL((k_sweep_wide<F, FWD, 16, MODE, TIn, TOut>), grid, block, 0, c->work, WIDE_ARGS); break;
+                default: hipLaunchKernelGGL((k_sweep_wide<F, FWD, 32, MODE, TIn, TOut>), grid, block, 0, c->work, WIDE_ARGS); break;
+            }
+            HIP_CHECK(hipGetLastError());
+        }
         return ICCG_OK;
     };
     if (FWD) {
@@ -1050,6 +1177,7 @@ int launch_sweep_t(iccg_ctx *c, const void *in, void *out, const CgArgs &cg) {
         for (int col = tail - 1; col >= 0; --col) ICCG_CHECK(per_color(col, nullptr));
     }
 #undef SWEEP_ARGS
+#undef WIDE_ARGS
     if (c->prof) c->prof->end(c->work, FWD ? PK_FWD : PK_BWD, launched);
     return ICCG_OK;
 }
@@ -1195,6 +1323,18 @@ int install_factor(iccg_ctx *c) {
             hipLaunchKernelGGL(k_fill_slots<double>, dim3(blocks), dim3(256), 0, c->work,
                                s->nslots, s->ssrc.p, c->lval.p, s->sval64.p);
         }
+        DevWide &w = s->wide;
+        if (w.nwide > 0) {
+            if (c->fp32()) {
+                if (!w.sval32.p) ICCG_CHECK(w.sval32.alloc(static_cast<size_t>(w.nslots)));
+                hipLaunchKernelGGL(k_fill_slots<float>, dim3(blocks), dim3(256), 0, c->work,
+                                   w.nslots, w.ssrc.p, c->lval.p, w.sval32.p);
+            } else {
+                if (!w.sval64.p) ICCG_CHECK(w.sval64.alloc(static_cast<size_t>(w.nslots)));
+                hipLaunchKernelGGL(k_fill_slots<double>, dim3(blocks), dim3(256), 0, c->work,
+                                   w.nslots, w.ssrc.p, c->lval.p, w.sval64.p);
+            }
+        }
     }
     if (c->fp32())
         hipLaunchKernelGGL(k_fill_inv<float>, dim3(blocks), dim3(256), 0, c->work, c->n,
@@ -1230,6 +1370,22 @@ int upload_sweep(iccg_ctx *c, const SweepPlan &plan, DevSweep &d) {
     ICCG_CHECK(d.meta.upload(plan.meta.data(), plan.meta.size(), c->work));
     ICCG_CHECK(d.scol.upload(plan.slot_col.data(), plan.slot_col.size(), c->work));
     ICCG_CHECK(d.ssrc.upload(plan.slot_src.data(), plan.slot_src.size(), c->work));
+    return ICCG_OK;
+}
+
+int upload_wide(iccg_ctx *c, const WidePlan &w, DevWide &d) {
+    d.nwide = static_cast<int>(w.task.size());
+    d.color_ptr = w.color_ptr;
+    if (d.nwide == 0) return ICCG_OK;
+    d.nslots = static_cast<long long>(w.slot_col.size());
+    ICCG_CHECK(d.task.upload(w.task.data(), w.task.size(), c->work));
+    ICCG_CHECK(d.piece_ptr.upload(w.piece_ptr.data(), w.piece_ptr.size(), c->work));
+    ICCG_CHECK(d.pieces.upload(w.pieces.data(), w.pieces.size(), c->work));
+    ICCG_CHECK(d.subs.upload(w.subs.data(), w.subs.size(), c->work));
+    ICCG_CHECK(d.wmeta.upload(w.wmeta.data(), w.wmeta.size(), c->work));
+    ICCG_CHECK(d.wlev.upload(w.wlev.data(), w.wlev.size(), c->work));
+    ICCG_CHECK(d.scol.upload(w.slot_col.data(), w.slot_col.size(), c->work));
+    ICCG_CHECK(d.ssrc.upload(w.slot_src.data(), w.slot_src.size(), c->work));
     return ICCG_OK;
 }
 
@@ -1303,7 +1459,7 @@ int validate(int n, const int *rowptr, const int *col, const double *val, int nb
 }
 
 int upload_setup(iccg_ctx *c, int n, const int *rowptr, const int *col, const double *val,
-                 int nblocks, int ncolors, const HostSetup &hs) {
+                 int nblocks, int ncolors, HostSetup &hs) {
     const int nnz = rowptr[n];
     c->n = n;
     c->nnz = nnz;
@@ -1322,6 +1478,13 @@ int upload_setup(iccg_ctx *c, int n, const int *rowptr, const int *col, const do
     ICCG_CHECK(c->val.upload(val, nnz, s));
     ICCG_CHECK(c->dpos.upload(hs.dpos.data(), n, s));
     ICCG_CHECK(c->tpos.upload(hs.tpos.data(), nnz, s));
+    if (c->opt.sweep_launch == 0 && c->opt.wide_blocks) {
+        for (SweepPlan *P : {&hs.fwd, &hs.bwd}) {
+            WidePlan wp;
+            ICCG_CHECK(build_wide_plan(*P, n, rowptr, col, hs.tpos.data(), ncolors, wp));
+            ICCG_CHECK(upload_wide(c, wp, P == &hs.fwd ? c->fwd.wide : c->bwd.wide));
+        }
+    }
     ICCG_CHECK(upload_sweep(c, hs.fwd, c->fwd));
     ICCG_CHECK(upload_sweep(c, hs.bwd, c->bwd));
     // hybrid sweeps: the trailing colors (in forward order) holding at most
@@ -1503,6 +1666,7 @@ void iccg_default_options(iccg_options *opt) {
     opt->sweep_launch = 0;
     opt->sweep_grid = 0;
     opt->flow_tail = 0;
+    opt->wide_blocks = 1;
 }
 
 const char *iccg_strerror(int st) {

@@ -79,6 +79,21 @@ struct DevArray {
     }
 };
 
+// Wide tasks of one sweep direction (WidePlan on the device).
+struct DevWide {
+    int nwide = 0;
+    long long nslots = 0;
+    std::vector<int> color_ptr;      // wide tasks of each color
+    DevArray<int> task, piece_ptr;
+    DevArray<WidePiece> pieces;
+    DevArray<Chunk> subs;
+    DevArray<uint32_t> wmeta;
+    DevArray<int> wlev;
+    DevArray<int> scol, ssrc;
+    DevArray<double> sval64;
+    DevArray<float> sval32;
+};
+
 struct DevSweep {
     int ntasks = 0;
     long long nslots = 0;
@@ -97,6 +112,7 @@ struct DevSweep {
     DevArray<int> flag_loc, flag_rem, deps, wg_task;   // dependency ranges sit in the task records
     long long ndeps = 0;
     long long remote_tasks = 0, exported_rows = 0;
+    DevWide wide;                   // per-color launches only
 };
 
 // Per-launch HIP-event timing of an instrumented (eager) solve.

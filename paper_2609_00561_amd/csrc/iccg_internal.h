@@ -52,7 +52,8 @@ struct TaskRec {
     int32_t c0, c1;
     int32_t dep0;
     int32_t kind_ndeps;   // kTaskRemote | kTaskExports | ndeps << 2
-    int32_t pad[4];
+    int32_t wide;         // index among the wide tasks (see WidePlan), or -1
+    int32_t pad[3];
     int nchunks() const { return c1 - c0; }
 };
 static_assert(sizeof(TaskRec) == 64, "TaskRec layout");
@@ -109,6 +110,42 @@ struct SweepPlan {
     long long remote_tasks = 0;        // tasks with kTaskRemote
     long long exported_rows = 0;       // rows with kMetaExport
 };
+
+// Wide tasks (per-color launches only).  A task that is one block of more
+// than kWideMinRows rows would otherwise run its 64-row chunks one after
+// another on one wavefront.  Instead a workgroup of kWideWaves wavefronts runs it in pieces
+// of up to kWideRows rows, in the sweep's processing order; each piece gets a
+// level schedule over all of its rows, so a level's rows anywhere in the piece
+// run together.  Per row: entries outside the piece first, then those inside
+// it, each group ascending; the piece's rows are stored as 64-row sub-chunks
+// in the padded slot layout.
+constexpr int kWideWaves = 8;
+constexpr int kWideRows = 64 * kWideWaves;
+// Smaller multi-chunk blocks stay on one wavefront: for a few chunks the
+// workgroup's barriers cost more than the sequence (measured on blocks of
+// 65-67 rows).
+constexpr int kWideMinRows = 256;
+struct WidePiece {
+    int32_t sub0, nsub;   // sub-chunks [sub0, sub0 + nsub) of WidePlan::subs
+    int32_t depth;        // levels of the piece
+    int32_t row0;         // first row of the piece
+};
+struct WidePlan {
+    std::vector<int> color_ptr;      // ncolors+1: wide tasks of each color
+    std::vector<int> task;           // task id of each wide task
+    std::vector<int> piece_ptr;      // nwide+1: pieces of each wide task, in processing order
+    std::vector<WidePiece> pieces;
+    std::vector<Chunk> subs;         // row0, off, shape (nrows | width << 16) of each sub-chunk
+    std::vector<uint32_t> wmeta;     // n: entries outside | entries inside << 16 (rows of wide tasks)
+    std::vector<int> wlev;           // n: level inside the piece
+    std::vector<int> slot_col, slot_src;
+    int max_depth = 0;
+};
+// Marks the tasks of plan that are single blocks of more than kWideMinRows
+// rows as wide and builds their pieces.  An empty WidePlan (no wide task) is
+// valid.
+int build_wide_plan(SweepPlan &plan, int n, const int *rowptr, const int *col, const int *tpos,
+                    int ncolors, WidePlan &out);
 
 // Sliced ELL copy of A' for the SpMV: slices of 64 consecutive rows; entry k
 // of the slice's row t at slice_off[s] + k*64 + t (column -1, value 0 pads).

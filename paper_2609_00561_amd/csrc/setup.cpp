@@ -217,7 +217,101 @@ int build_sweep_plan(bool forward, int n, const int *rowptr, const int *col, con
         if (nd >= (1 << 29)) return set_error(ICCG_EINVAL, "a task has too many dependencies");
         tr.dep0 = out.dep_ptr[t];
         tr.kind_ndeps = kind[t] | (nd << 2);
+        tr.wide = -1;
         tr.first = out.chunks[forward ? tr.c0 : tr.c1 - 1];
+    }
+    return ICCG_OK;
+}
+
+int build_wide_plan(SweepPlan &plan, int n, const int *rowptr, const int *col, const int *tpos,
+                    int ncolors, WidePlan &out) {
+    out = WidePlan();
+    const bool fwd = plan.forward;
+    out.color_ptr.assign(1, 0);
+    out.piece_ptr.assign(1, 0);
+    out.wmeta.assign(n, 0);
+    out.wlev.assign(n, 0);
+    std::vector<int> lev(kWideRows), ord;
+    std::vector<std::vector<int>> outside(kWideRows), inside(kWideRows);
+    for (int c = 0; c < ncolors; ++c) {
+        for (int t = plan.color_task_ptr[c]; t < plan.color_task_ptr[c + 1]; ++t) {
+            TaskRec &tr = plan.tasks[t];
+            if (tr.c1 - tr.c0 < 2) continue;
+            // one block [r0, r1) cut into 64-row chunks
+            const int r0 = plan.chunks[tr.c0].row0;
+            const int r1 = plan.chunks[tr.c1 - 1].row0 + plan.chunks[tr.c1 - 1].nrows();
+            if (r1 - r0 <= kWideMinRows) continue;
+            tr.wide = static_cast<int>(out.task.size());
+            out.task.push_back(t);
+            const int npieces = (r1 - r0 + kWideRows - 1) / kWideRows;
+            for (int q = 0; q < npieces; ++q) {
+                const int pi = fwd ? q : npieces - 1 - q;
+                const int p0 = r0 + pi * kWideRows, p1 = std::min(r1, p0 + kWideRows), np = p1 - p0;
+                // levels in the sweep's row order
+                int depth = 0;
+                for (int step = 0; step < np; ++step) {
+                    const int u = fwd ? step : np - 1 - step;
+                    const int i = p0 + u;
+                    outside[u].clear();
+                    inside[u].clear();
+                    int l = 0;
+                    for (int k = rowptr[i]; k < rowptr[i + 1]; ++k) {
+                        const int j = col[k];
+                        if (fwd ? (j >= i) : (j <= i)) continue;
+                        if (j >= p0 && j < p1) {
+                            inside[u].push_back(k);
+                            l = std::max(l, lev[j - p0] + 1);
+                        } else {
+                            outside[u].push_back(k);
+                        }
+                    }
+                    if (outside[u].size() > 0xffff || inside[u].size() > 0xffff)
+                        return set_error(ICCG_EINVAL, "a row has more than 65535 entries in one triangle");
+                    lev[u] = l;
+                    depth = std::max(depth, l + 1);
+                    out.wmeta[i] = static_cast<uint32_t>(outside[u].size()) |
+                                   (static_cast<uint32_t>(inside[u].size()) << 16);
+                    out.wlev[i] = l;
+                }
+                WidePiece P{};
+                P.sub0 = static_cast<int>(out.subs.size());
+                P.depth = depth;
+                P.row0 = p0;
+                for (int s0 = p0; s0 < p1; s0 += kChunkRows) {
+                    const int nr = std::min(kChunkRows, p1 - s0);
+                    int width = 0;
+                    for (int u = s0 - p0; u < s0 - p0 + nr; ++u)
+                        width = std::max(width, static_cast<int>(outside[u].size() + inside[u].size()));
+                    const long long off = static_cast<long long>(out.slot_col.size());
+                    if (off + static_cast<long long>(width) * nr >= (1LL << 31))
+                        return set_error(ICCG_EINVAL, "wide schedule exceeds 2^31 slots");
+                    Chunk ch{};
+                    ch.row0 = s0;
+                    ch.off = static_cast<int32_t>(off);
+                    ch.shape = nr | (width << 16);
+                    ch.depth = depth;
+                    out.subs.push_back(ch);
+                    out.slot_col.resize(off + static_cast<long long>(width) * nr, -1);
+                    out.slot_src.resize(off + static_cast<long long>(width) * nr, -1);
+                    for (int r = 0; r < nr; ++r) {
+                        const int u = s0 - p0 + r;
+                        int k = 0;
+                        for (const auto *grp : {&outside[u], &inside[u]})
+                            for (int e : *grp) {
+                                const long long slot = off + static_cast<long long>(k) * nr + r;
+                                out.slot_col[slot] = col[e];
+                                out.slot_src[slot] = fwd ? e : tpos[e];
+                                ++k;
+                            }
+                    }
+                }
+                P.nsub = static_cast<int>(out.subs.size()) - P.sub0;
+                out.pieces.push_back(P);
+                out.max_depth = std::max(out.max_depth, depth);
+            }
+            out.piece_ptr.push_back(static_cast<int>(out.pieces.size()));
+        }
+        out.color_ptr.push_back(static_cast<int>(out.task.size()));
     }
     return ICCG_OK;
 }

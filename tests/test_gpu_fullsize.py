@@ -206,6 +206,33 @@ def test_knn1m_leiden_cpm_apply_and_solve(knn):
         assert true <= 2e-8
 
 
+def test_knn1m_leiden_md_wide_blocks(knn):
+    """Leiden-MD on the kNN graph: 74 communities of up to 25,455 rows, run
+    by workgroups in level-scheduled pieces of 512 rows.  IC application
+    element by element against the oracle; the solve by its true residual."""
+    A, b = knn
+    o = iccg.iccg_order_leiden(A, "modularity", 1.0)
+    rp, cl, vl = iccg.iccg_permute(A, o.perm)
+    Ap = oracle.permute(A, o.perm)
+    lval, brk = oracle.ic0(Ap)
+    assert brk < 0
+    r = np.random.default_rng(16).uniform(-1, 1, A.n)
+    want = oracle.ic_apply(Ap, lval, r)
+    with iccg.Context(rp, cl, vl, o.block_ptr, o.color_ptr) as ctx:
+        ctx.ic0_factor()
+        zd = torch.zeros(A.n, dtype=torch.float64, device="cuda")
+        ctx.ic_apply(_dev(r), zd)
+        err = _rel_inf(_host(zd), want)
+        print("knn 1M Leiden-MD apply rel err", err, "blocks", o.nblocks, "colors", o.ncolors)
+        assert err <= 1e-12
+        xd = torch.zeros(A.n, dtype=torch.float64, device="cuda")
+        res = ctx.solve(_dev(b[np.asarray(o.perm)]), xd, tol=1e-8)
+        assert res["status"] == iccg.ICCG_OK
+        true = _true_relres(A, o.perm, _host(xd), b)
+        print("knn 1M Leiden-MD iters", res["iters"], "true relres", true)
+        assert true <= 2e-8
+
+
 def test_stencil27_96_fp32_form():
     A, b = _workload("stencil27_96")
     o = iccg.iccg_order_abmc(A, 32)

@@ -350,7 +350,9 @@ def test_single_launch_sweep_identical_to_per_color(case, precision):
     computes the same per-row terms as one launch per color: outputs and
     solves are bit-identical.  Small persistent grids (8 and 64 workgroups)
     make every workgroup run many tasks in sequence; the hybrid mode runs
-    the small colors as one dataflow launch, here with three tail sizes."""
+    the small colors as one dataflow launch, here with three tail sizes.
+    All run blocks of more than 64 rows in 64-row chunks (the dataflow
+    modes always do)."""
     cs = _case(*case)
     Ap = cs[4]
     r = np.random.default_rng(8).standard_normal(Ap.n)
@@ -359,7 +361,8 @@ def test_single_launch_sweep_identical_to_per_color(case, precision):
     # the dataflow launch, if any) and unbounded (every color in it)
     for mode, grid, tail in (("per_color", 0, 0), ("single", 0, 0), ("single", 8, 0), ("single", 64, 0),
                              ("hybrid", 0, 0), ("hybrid", 0, 1), ("hybrid", 0, 1 << 30)):
-        with _ctx(cs, sweep_launch=mode, sweep_grid=grid, flow_tail=tail, precision=precision) as ctx:
+        with _ctx(cs, sweep_launch=mode, sweep_grid=grid, flow_tail=tail, precision=precision,
+                  wide_blocks=False) as ctx:
             zd = torch.zeros(Ap.n, dtype=torch.float64, device="cuda")
             for _ in range(3):                      # repeated launches reuse the epoch flags
                 ctx.ic_apply(_dev(r), zd)
@@ -370,3 +373,35 @@ def test_single_launch_sweep_identical_to_per_color(case, precision):
     for k in range(1, len(outs)):
         assert np.array_equal(outs[0], outs[k]), k
         assert sols[0][0] == sols[k][0] and np.array_equal(sols[0][1], sols[k][1]), k
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("case", [CASES[3], ("knn13_20k", "leiden", ("modularity", 1.0)),
+                                  ("stencil27_12", "abmc", 300), ("randspd_2k", "abmc", 300)], ids=_ids)
+def test_wide_blocks_match_chunks(case, precision):
+    """Blocks of more than 64 rows run by a workgroup in level-scheduled
+    pieces (the default) against one wavefront in 64-row chunks.  The forward
+    sweep sums every row in ascending column order either way, so it is
+    bit-identical.  The backward sweep groups each row's terms by piece
+    instead of by chunk: equal up to rounding.  Both agree with the oracle."""
+    cs = _case(*case)
+    Ap, lval = cs[4], cs[5]
+    r = np.random.default_rng(9).standard_normal(Ap.n)
+    res = {}
+    for wide in (True, False):
+        with _ctx(cs, precision=precision, wide_blocks=wide) as ctx:
+            yd = torch.zeros(Ap.n, dtype=torch.float64, device="cuda")
+            ctx.ic_forward(_dev(r), yd)
+            zd = torch.zeros_like(yd)
+            ctx.ic_apply(_dev(r), zd)
+            xd = torch.zeros_like(yd)
+            sol = ctx.solve(_dev(cs[6]), xd)
+            res[wide] = (_host(yd), _host(zd), sol, _host(xd))
+    (y1, z1, s1, x1), (y0, z0, s0, x0) = res[True], res[False]
+    assert np.array_equal(y1, y0)
+    tol = 1e-12 if precision == "fp64" else 1e-5
+    assert _rel_inf(z1, z0) <= tol
+    if precision == "fp64":
+        assert _rel_inf(z1, oracle.ic_apply(Ap, lval, r)) <= 1e-12
+    assert s1["status"] == iccg.ICCG_OK and abs(s1["iters"] - s0["iters"]) <= 2
+    assert np.linalg.norm(x1 - x0) <= 1e-6 * np.linalg.norm(x0)

@@ -213,7 +213,7 @@ def test_default_options():
     opt = iccg._Options()
     iccg.load().iccg_default_options(ctypes.byref(opt))
     assert (opt.precision, opt.check_every, opt.pack_rows, opt.use_graph) == (iccg.ICCG_FP64, 32, 64, 1)
-    assert (opt.sweep_launch, opt.sweep_grid, opt.flow_tail) == (0, 0, 0)
+    assert (opt.sweep_launch, opt.sweep_grid, opt.flow_tail, opt.wide_blocks) == (0, 0, 0, 1)
 
 
 def test_setup_rejects_bad_options():
