@@ -710,20 +710,20 @@ __global__ __launch_bounds__(64 * kSweepWaves) void k_sweep(const TaskRec *__res
 }
 
 // Wide task (see WidePlan): one block of more than 64 rows, run piece by
-// piece by a workgroup of kWideWaves wavefronts.  Wavefront w takes
+// piece by a workgroup of WAVES wavefronts.  Wavefront w takes
 // sub-chunk w of the piece, one lane per row.  Terms from outside the piece
 // are gathered first (earlier pieces of the block were stored by this
 // workgroup before the barrier that ends them); then the piece's levels run
 // with a workgroup barrier after each, the values passing through LDS.
-template <typename F, bool FWD, int KMAX, int MODE, typename TIn, typename TOut>
-__global__ __launch_bounds__(64 * kWideWaves) void k_sweep_wide(
+template <typename F, bool FWD, int KMAX, int MODE, typename TIn, typename TOut, int WAVES>
+__global__ __launch_bounds__(64 * WAVES) void k_sweep_wide(
     const int *__restrict__ wtask, const int *__restrict__ piece_ptr,
     const WidePiece *__restrict__ pieces, const Chunk *__restrict__ subs,
     const uint32_t *__restrict__ wmeta, const int *__restrict__ wlev, const int *__restrict__ scol,
     const F *__restrict__ sval, const F *__restrict__ inv, int w_base, const TIn *__restrict__ in,
     TOut *__restrict__ out, CgArgs cg) {
     if (cg.sc && cg.sc->done != DONE_RUNNING) return;
-    __shared__ F ys[kWideRows];
+    __shared__ F ys[64 * WAVES];
     const int t = static_cast<int>(threadIdx.x) & 63;
     const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) >> 6);
     const int w = w_base + static_cast<int>(blockIdx.x);
@@ -808,7 +808,7 @@ __global__ __launch_bounds__(64 * kWideWaves) void k_sweep_wide(
         __syncthreads();
     }
     if (MODE != SW_APPLY) {
-        const double tsum = block_sum<64 * kWideWaves>(dacc);
+        const double tsum = block_sum<64 * WAVES>(dacc);
         if (threadIdx.x == 0) cg.part[wtask[w]] = tsum;
     }
 }
@@ -1145,12 +1145,14 @@ int launch_sweep_t(iccg_ctx *c, const void *in, void *out, const CgArgs &cg) {
         }
         if (nw > 0) {
             ++launched;
-            const dim3 grid(nw), block(64 * kWideWaves);
+            // the piece size the plan was built with: 64 rows per wavefront,
+            // wide_waves(max width) wavefronts
+            const dim3 grid(nw), block(64 * wide_waves(d.max_width));
             switch (d.kmax) {
-                case 4: hipLaunchKernelGGL((k_sweep_wide<F, FWD, 4, MODE, TIn, TOut>), grid, block, 0, c->work, WIDE_ARGS); break;
-                case 8: hipLaunchKernelGGL((k_sweep_wide<F, FWD, 8, MODE, TIn, TOut>), grid, block, 0, c->work, WIDE_ARGS); break;
-                case 16: hipLaunchKernelGGL((k_sweep_wide<F, FWD, 16, MODE, TIn, TOut>), grid, block, 0, c->work, WIDE_ARGS); break;
-                default: hipLaunchKernelGGL((k_sweep_wide<F, FWD, 32, MODE, TIn, TOut>), grid, block, 0, c->work, WIDE_ARGS); break;
+                case 4: hipLaunchKernelGGL((k_sweep_wide<F, FWD, 4, MODE, TIn, TOut, wide_waves(4)>), grid, block, 0, c->work, WIDE_ARGS); break;
+                case 8: hipLaunchKernelGGL((k_sweep_wide<F, FWD, 8, MODE, TIn, TOut, wide_waves(8)>), grid, block, 0, c->work, WIDE_ARGS); break;
+                case 16: hipLaunchKernelGGL((k_sweep_wide<F, FWD, 16, MODE, TIn, TOut, wide_waves(16)>), grid, block, 0, c->work, WIDE_ARGS); break;
+                default: hipLaunchKernelGGL((k_sweep_wide<F, FWD, 32, MODE, TIn, TOut, wide_waves(32)>), grid, block, 0, c->work, WIDE_ARGS); break;
             }
             HIP_CHECK(hipGetLastError());
         }
@@ -1481,7 +1483,8 @@ int upload_setup(iccg_ctx *c, int n, const int *rowptr, const int *col, const do
     if (c->opt.sweep_launch == 0 && c->opt.wide_blocks) {
         for (SweepPlan *P : {&hs.fwd, &hs.bwd}) {
             WidePlan wp;
-            ICCG_CHECK(build_wide_plan(*P, n, rowptr, col, hs.tpos.data(), ncolors, wp));
+            ICCG_CHECK(build_wide_plan(*P, n, rowptr, col, hs.tpos.data(), ncolors,
+                                       64 * wide_waves(P->max_width), wp));
             ICCG_CHECK(upload_wide(c, wp, P == &hs.fwd ? c->fwd.wide : c->bwd.wide));
         }
     }

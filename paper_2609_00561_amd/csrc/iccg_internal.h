@@ -113,14 +113,17 @@ struct SweepPlan {
 
 // Wide tasks (per-color launches only).  A task that is one block of more
 // than kWideMinRows rows would otherwise run its 64-row chunks one after
-// another on one wavefront.  Instead a workgroup of kWideWaves wavefronts runs it in pieces
-// of up to kWideRows rows, in the sweep's processing order; each piece gets a
-// level schedule over all of its rows, so a level's rows anywhere in the piece
-// run together.  Per row: entries outside the piece first, then those inside
+// another on one wavefront.  Instead a workgroup of wide_waves(width)
+// wavefronts runs it in pieces of 64 rows per wavefront, in the sweep's
+// processing order; each piece gets a level schedule over all of its rows, so
+// a level's rows anywhere in the piece run together.  Per row: entries outside the piece first, then those inside
 // it, each group ascending; the piece's rows are stored as 64-row sub-chunks
 // in the padded slot layout.
-constexpr int kWideWaves = 8;
-constexpr int kWideRows = 64 * kWideWaves;
+// Wavefronts per wide workgroup: 16 when every row of the schedule has at
+// most 8 entries (the kernel's registers then allow 16 wavefronts on a
+// compute unit), else 8.
+constexpr int wide_waves(int max_width) { return max_width <= 8 ? 16 : 8; }
+constexpr int kWideMaxRows = 64 * 16;
 // Smaller multi-chunk blocks stay on one wavefront: for a few chunks the
 // workgroup's barriers cost more than the sequence (measured on blocks of
 // 65-67 rows).
@@ -145,7 +148,7 @@ struct WidePlan {
 // rows as wide and builds their pieces.  An empty WidePlan (no wide task) is
 // valid.
 int build_wide_plan(SweepPlan &plan, int n, const int *rowptr, const int *col, const int *tpos,
-                    int ncolors, WidePlan &out);
+                    int ncolors, int piece_rows, WidePlan &out);
 
 // Sliced ELL copy of A' for the SpMV: slices of 64 consecutive rows; entry k
 // of the slice's row t at slice_off[s] + k*64 + t (column -1, value 0 pads).

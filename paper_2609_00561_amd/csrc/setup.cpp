@@ -224,15 +224,17 @@ int build_sweep_plan(bool forward, int n, const int *rowptr, const int *col, con
 }
 
 int build_wide_plan(SweepPlan &plan, int n, const int *rowptr, const int *col, const int *tpos,
-                    int ncolors, WidePlan &out) {
+                    int ncolors, int piece_rows, WidePlan &out) {
     out = WidePlan();
     const bool fwd = plan.forward;
     out.color_ptr.assign(1, 0);
     out.piece_ptr.assign(1, 0);
     out.wmeta.assign(n, 0);
     out.wlev.assign(n, 0);
-    std::vector<int> lev(kWideRows), ord;
-    std::vector<std::vector<int>> outside(kWideRows), inside(kWideRows);
+    if (piece_rows < kChunkRows || piece_rows > kWideMaxRows || piece_rows % kChunkRows)
+        return set_error(ICCG_EINVAL, "wide piece size");
+    std::vector<int> lev(piece_rows);
+    std::vector<std::vector<int>> outside(piece_rows), inside(piece_rows);
     for (int c = 0; c < ncolors; ++c) {
         for (int t = plan.color_task_ptr[c]; t < plan.color_task_ptr[c + 1]; ++t) {
             TaskRec &tr = plan.tasks[t];
@@ -243,10 +245,10 @@ int build_wide_plan(SweepPlan &plan, int n, const int *rowptr, const int *col, c
             if (r1 - r0 <= kWideMinRows) continue;
             tr.wide = static_cast<int>(out.task.size());
             out.task.push_back(t);
-            const int npieces = (r1 - r0 + kWideRows - 1) / kWideRows;
+            const int npieces = (r1 - r0 + piece_rows - 1) / piece_rows;
             for (int q = 0; q < npieces; ++q) {
                 const int pi = fwd ? q : npieces - 1 - q;
-                const int p0 = r0 + pi * kWideRows, p1 = std::min(r1, p0 + kWideRows), np = p1 - p0;
+                const int p0 = r0 + pi * piece_rows, p1 = std::min(r1, p0 + piece_rows), np = p1 - p0;
                 // levels in the sweep's row order
                 int depth = 0;
                 for (int step = 0; step < np; ++step) {

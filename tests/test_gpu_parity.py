@@ -376,11 +376,13 @@ def test_single_launch_sweep_identical_to_per_color(case, precision):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
-@pytest.mark.parametrize("case", [CASES[3], ("knn13_20k", "leiden", ("modularity", 1.0)),
+@pytest.mark.parametrize("case", [CASES[3], ("poisson7_32", "leiden", ("modularity", 1.0)),
+                                  ("knn13_20k", "leiden", ("modularity", 1.0)),
                                   ("stencil27_12", "abmc", 300), ("randspd_2k", "abmc", 300)], ids=_ids)
 def test_wide_blocks_match_chunks(case, precision):
-    """Blocks of more than 64 rows run by a workgroup in level-scheduled
-    pieces (the default) against one wavefront in 64-row chunks.  The forward
+    """Blocks of more than 256 rows run by a workgroup in level-scheduled
+    pieces (the default; 1024-row pieces for the 7-point matrices, 512 for the
+    wider ones) against one wavefront in 64-row chunks.  The forward
     sweep sums every row in ascending column order either way, so it is
     bit-identical.  The backward sweep groups each row's terms by piece
     instead of by chunk: equal up to rounding.  Both agree with the oracle."""
