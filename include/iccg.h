@@ -87,9 +87,12 @@ typedef struct {
     int   flow_tail;    /* hybrid sweeps: at most this many tasks in the dataflow
                            part (0 = 700)                                       */
     int   wide_blocks;  /* per-color launches: a block of more than 256 rows is
-                           run by a workgroup of 8 wavefronts in pieces of 512
-                           rows, each piece level-scheduled as a whole (1,
-                           default), or by one wavefront in 64-row chunks (0).
+                           run by one workgroup in pieces of 64 rows per
+                           wavefront, each piece level-scheduled as a whole (1,
+                           default): 16 wavefronts and 1,024-row pieces when no
+                           row of the sweep has more than 8 entries, else 8
+                           wavefronts and 512-row pieces; or (0) by one
+                           wavefront in 64-row chunks.
                            The forward sweep is bit-identical either way; the
                            backward sweep's per-row sums group the entries by
                            piece instead of by chunk (equal up to rounding).   */
@@ -127,6 +130,19 @@ int iccg_order_abmc(int n, const int *rowptr, const int *col, int block_size,
 int iccg_order_leiden(int n, const int *rowptr, const int *col, int quality, double gamma,
                       double beta, int n_iter, uint64_t seed,
                       int *perm, int *nblocks, int *block_ptr, int *ncolors, int *color_ptr);
+
+/*
+ * Load-imbalance statistics of an ordering (Section 7.3, Table 6):
+ * out[0] n_b, out[1] n_c, out[2] the Gini coefficient G of the block sizes
+ * (sum over all ordered pairs of |s_i - s_j| divided by 2 n_b^2 times the mean
+ * size), out[3] B_max, out[4] B_max / B_avg, out[5] C_max / C_avg (rows of the
+ * largest color over the mean rows per color).  block_ptr[nblocks+1] and
+ * color_ptr[ncolors+1] as returned by the ordering calls; out: host double[6].
+ * ICCG_EBADORDER for an empty block or color or pointers that do not start at
+ * 0; host only.
+ */
+int iccg_block_stats(int nblocks, const int *block_ptr, int ncolors, const int *color_ptr,
+                     double *out);
 
 /*
  * A' = P A P^T (perm[new] = old) with sorted columns.  prow[n+1], pcol[nnz],
@@ -243,6 +259,9 @@ typedef struct {
     long long remote_tasks;         /* single-launch sweep (forward schedule):
                                        tasks with a dependency in another region  */
     long long exported_rows;        /* rows written through for other regions     */
+    double gini;                    /* Table 6 statistics of the context's ordering */
+    double bmax_over_avg;           /* (as iccg_block_stats)                      */
+    double cmax_over_avg;
 } iccg_info;
 
 int iccg_get_info(iccg_ctx *c, iccg_info *info);
@@ -290,6 +309,13 @@ int  iccg_mpnn_train_step(iccg_mpnn *m, iccg_ctx *c, const double *probes, int n
  * upper part 0), ready for iccg_set_factor.  bf16 = 1 stores weights and
  * activations in BF16 (FP32 accumulation); 0 runs in FP32. */
 int  iccg_mpnn_predict(iccg_mpnn *m, iccg_ctx *c, int bf16, double *lvals);
+/* Smoothed training probes for the matrix of context c: for each of the
+ * nprobes rows z_i of the DEVICE FP64 array z[nprobes][n] (row-major, drawn by
+ * the caller), out_i = D^{1/2} M^{-1} D^{1/2} z_i rescaled to 2-norm sqrt(n),
+ * with D = diag(A') and M = L L^T the context's current factor (the plain
+ * IC(0) factor for training).  out: DEVICE FP64 [nprobes][n], not aliasing z.
+ * ICCG_ESTATE without a factor. */
+int  iccg_mpnn_smooth_probes(iccg_ctx *c, const double *z, int nprobes, double *out);
 void iccg_mpnn_destroy(iccg_mpnn *m);
 
 /* Host only: no device call, no context.  Checks the permuted system and its

@@ -357,6 +357,24 @@ __global__ __launch_bounds__(kVecThreads) void k_axpy_alpha(int n, double *__res
         x[i] = x[i] + alpha * p[i];
 }
 
+// out_i = sqrt(a'_ii) in_i (the diagonal scaling of the learned form's probes)
+__global__ __launch_bounds__(kVecThreads) void k_scale_sqrt_diag(int n, const int *__restrict__ dpos,
+                                                                 const double *__restrict__ val,
+                                                                 const double *__restrict__ in,
+                                                                 double *__restrict__ out) {
+    for (int i = blockIdx.x * kVecThreads + threadIdx.x; i < n; i += gridDim.x * kVecThreads)
+        out[i] = sqrt(val[dpos[i]]) * in[i];
+}
+
+// v *= target / sqrt(*sumsq)
+__global__ __launch_bounds__(kVecThreads) void k_rescale_to_norm(int n, double *__restrict__ v,
+                                                                 const double *__restrict__ sumsq,
+                                                                 double target) {
+    const double f = target / sqrt(*sumsq);
+    for (int i = blockIdx.x * kVecThreads + threadIdx.x; i < n; i += gridDim.x * kVecThreads)
+        v[i] = v[i] * f;
+}
+
 template <typename A, typename B>
 __global__ __launch_bounds__(kVecThreads) void k_convert(int n, A *__restrict__ dst,
                                                          const B *__restrict__ src) {
@@ -1247,9 +1265,10 @@ int launch_reduce(iccg_ctx *c, int np, int op, double *out) {
 }
 
 // One CG iteration (all kernels return at once after the stopping test passed):
-//   1. p = z + beta p (beta = 0 and p = 0 before the first iteration)
+//   1. x += alpha p (the previous iteration's step, deferred to here), then
+//      p = z + beta p (alpha = beta = 0 and p = 0 before the first iteration)
 //   2. SpMV:     q = A p, alpha = rho / (p, q)
-//   3. forward:  x += alpha p, r -= alpha q, ||r||^2 partials, y = L^{-1} r
+//   3. forward:  r -= alpha q, ||r||^2 partials, y = L^{-1} r
 //   4. backward: z = L^{-T} y, (r, z) partials
 //   5. stopping test on ||r||, then beta = (r, z)/rho, rho = (r, z)
 int enqueue_iteration(iccg_ctx *c, long long j) {
@@ -1714,6 +1733,7 @@ int iccg_setup(iccg_ctx **out, int n, const int *rowptr, const int *col, const d
         HostSetup hs;
         ICCG_CHECK(validate(n, rowptr, col, val, nblocks, block_ptr, ncolors, color_ptr,
                             c->opt.pack_rows, hs));
+        ICCG_CHECK(iccg_block_stats(nblocks, block_ptr, ncolors, color_ptr, c->stats6));
         c->user = static_cast<hipStream_t>(c->opt.stream);
         HIP_CHECK(hipStreamCreateWithFlags(&c->work, hipStreamNonBlocking));
         int dev = 0;
@@ -1876,6 +1896,31 @@ int iccg_dot(iccg_ctx *c, const double *a, const double *b, double *out_host) {
     });
 }
 
+int iccg_mpnn_smooth_probes(iccg_ctx *c, const double *z, int nprobes, double *out) {
+    return entry(c, [&]() -> int {
+        if (!z || !out || nprobes < 1) return set_error(ICCG_EINVAL, "need z, out and nprobes >= 1");
+        if (!c->has_factor) return set_error(ICCG_ESTATE, "no factor");
+        ICCG_CHECK(flow_guard(c, 2LL * nprobes));
+        const int n = c->n;
+        const dim3 grid(c->vec_blocks), block(kVecThreads);
+        for (int i = 0; i < nprobes; ++i) {
+            const double *zi = z + static_cast<size_t>(i) * n;
+            double *oi = out + static_cast<size_t>(i) * n;
+            hipLaunchKernelGGL(k_scale_sqrt_diag, grid, block, 0, c->work, n, c->dpos.p, c->val.p, zi, c->r.p);
+            HIP_CHECK(hipGetLastError());
+            ICCG_CHECK((launch_sweep<true, SW_APPLY>(c, c->r.p, ytmp(c), no_cg())));
+            ICCG_CHECK((launch_sweep<false, SW_APPLY>(c, ytmp(c), c->z.p, no_cg())));
+            hipLaunchKernelGGL(k_scale_sqrt_diag, grid, block, 0, c->work, n, c->dpos.p, c->val.p, c->z.p, oi);
+            HIP_CHECK(hipGetLastError());
+            ICCG_CHECK(enqueue_dot(c, oi, oi, OP_STORE, c->q.p));
+            hipLaunchKernelGGL(k_rescale_to_norm, grid, block, 0, c->work, n, oi, c->q.p,
+                               std::sqrt(static_cast<double>(n)));
+            HIP_CHECK(hipGetLastError());
+        }
+        return check_sweep_err(c);
+    });
+}
+
 int iccg_solve(iccg_ctx *c, const double *b, double *x, double tol, int maxit, int *iters,
                double *relres, double *relres_true) {
     return entry(c, [&]() -> int { return solve_impl(c, b, x, tol, maxit, iters, relres, relres_true); });
@@ -1970,6 +2015,9 @@ int iccg_get_info(iccg_ctx *c, iccg_info *info) {
     info->sweep_resident = c->last_resident;
     info->remote_tasks = c->fwd.remote_tasks;
     info->exported_rows = c->fwd.exported_rows;
+    info->gini = c->stats6[2];
+    info->bmax_over_avg = c->stats6[4];
+    info->cmax_over_avg = c->stats6[5];
     return ICCG_OK;
 }
 

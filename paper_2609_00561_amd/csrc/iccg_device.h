@@ -170,6 +170,7 @@ void destroy_learned_features(LearnedFeatures *f);
 struct iccg_ctx {
     Profiler *prof = nullptr;     // set only during iccg_profile_solve
     int n = 0, nnz = 0, nnz_lower = 0, nblocks = 0, ncolors = 0, max_block = 0;
+    double stats6[6] = {0, 0, 0, 0, 0, 0};   // iccg_block_stats of the ordering
     iccg_options opt{};
     hipStream_t user = nullptr;   // caller's stream
     hipStream_t work = nullptr;   // internal stream (graph capture needs a non-null stream)

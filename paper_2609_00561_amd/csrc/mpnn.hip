@@ -898,8 +898,10 @@ int iccg_mpnn_train_step(iccg_mpnn *m, iccg_ctx *c, const double *probes, int np
         ICCG_CHECK(probe_loss(m, c, probes, nprobes));
         ICCG_CHECK(backward(m, c));
         m->step += 1;
-        const float c1 = 1.0f - std::pow(0.9f, static_cast<float>(m->step));
-        const float c2 = 1.0f - std::pow(0.999f, static_cast<float>(m->step));
+        // bias corrections in FP64 first: 1 - 0.999f would carry 0.999's FP32
+        // representation error (1.3e-5 relative) into the first steps
+        const float c1 = static_cast<float>(1.0 - std::pow(0.9, static_cast<double>(m->step)));
+        const float c2 = static_cast<float>(1.0 - std::pow(0.999, static_cast<double>(m->step)));
         hipLaunchKernelGGL(k_adam, dim3(grid_of(kL.total, 256)), dim3(256), 0, m->work, kL.total, m->theta.p,
                            m->grad.p, m->m.p, m->v.p, lr, c1, c2);
         HIP_CHECK(hipGetLastError());

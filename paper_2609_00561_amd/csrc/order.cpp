@@ -530,3 +530,45 @@ extern "C" int iccg_permute(int n, const int *rowptr, const int *col, const doub
         return set_error(ICCG_ENOMEM, "host allocation failed in iccg_permute");
     }
 }
+
+// Load-imbalance statistics of an ordering (Section 7.3, Table 6).  The Gini
+// sum over ordered pairs, sum_i sum_j |s_i - s_j|, is taken exactly in
+// integers from the sorted sizes: the k-th smallest size (0-based) is the
+// larger element of k pairs and the smaller of n_b - 1 - k, so the sum is
+// 2 sum_k (2k - n_b + 1) s_(k).
+extern "C" int iccg_block_stats(int nblocks, const int *block_ptr, int ncolors, const int *color_ptr,
+                                double *out) {
+    try {
+        if (!out || !block_ptr || !color_ptr || nblocks < 1 || ncolors < 1)
+            return set_error(ICCG_EINVAL, "need nblocks, ncolors >= 1, block_ptr, color_ptr and out");
+        if (block_ptr[0] != 0 || color_ptr[0] != 0 || color_ptr[ncolors] != nblocks)
+            return set_error(ICCG_EBADORDER, "block_ptr/color_ptr must start at 0 and color_ptr end at nblocks");
+        std::vector<long long> s(nblocks);
+        for (int b = 0; b < nblocks; ++b) {
+            s[b] = static_cast<long long>(block_ptr[b + 1]) - block_ptr[b];
+            if (s[b] <= 0) return set_error(ICCG_EBADORDER, "empty or reversed block");
+        }
+        const long long n = block_ptr[nblocks];
+        long long cmax = 0;
+        for (int c = 0; c < ncolors; ++c) {
+            if (color_ptr[c + 1] <= color_ptr[c]) return set_error(ICCG_EBADORDER, "empty or reversed color");
+            cmax = std::max(cmax, static_cast<long long>(block_ptr[color_ptr[c + 1]]) - block_ptr[color_ptr[c]]);
+        }
+        std::vector<long long> sorted(s);
+        std::sort(sorted.begin(), sorted.end());
+        long long pairs = 0;
+        for (int k = 0; k < nblocks; ++k) pairs += (2LL * k - nblocks + 1) * sorted[k];
+        pairs *= 2;
+        const double nb = static_cast<double>(nblocks);
+        const double mean_block = static_cast<double>(n) / nb;
+        out[0] = nb;
+        out[1] = static_cast<double>(ncolors);
+        out[2] = static_cast<double>(pairs) / (2.0 * nb * nb * mean_block);
+        out[3] = static_cast<double>(sorted.back());
+        out[4] = static_cast<double>(sorted.back()) / mean_block;
+        out[5] = static_cast<double>(cmax) / (static_cast<double>(n) / static_cast<double>(ncolors));
+        return ICCG_OK;
+    } catch (const std::bad_alloc &) {
+        return set_error(ICCG_ENOMEM, "host allocation failed in iccg_block_stats");
+    }
+}

@@ -40,10 +40,11 @@ EXPORTS = [
     "iccg_setup", "ic0_factor", "iccg_set_factor", "iccg_restore_ic0", "iccg_get_factor", "ic_apply",
     "ic_forward", "ic_backward", "iccg_spmv", "iccg_dot", "iccg_solve",
     "iccg_residual_history", "iccg_profile_solve", "iccg_get_info", "iccg_schedule_stats",
+    "iccg_block_stats",
     "iccg_strerror", "iccg_last_error",
     "iccg_destroy", "iccg_mpnn_param_count", "iccg_mpnn_create", "iccg_mpnn_get_params",
     "iccg_mpnn_set_params", "iccg_mpnn_loss_grad", "iccg_mpnn_train_step", "iccg_mpnn_predict",
-    "iccg_mpnn_destroy",
+    "iccg_mpnn_destroy", "iccg_mpnn_smooth_probes",
 ]
 
 
@@ -70,7 +71,8 @@ class _Info(ctypes.Structure):
                 ("sweep_bytes", ctypes.c_double), ("spmv_bytes", ctypes.c_double),
                 ("last_solve_ms", ctypes.c_double), ("last_iters", ctypes.c_int),
                 ("sweep_resident", ctypes.c_int), ("remote_tasks", ctypes.c_longlong),
-                ("exported_rows", ctypes.c_longlong)]
+                ("exported_rows", ctypes.c_longlong), ("gini", ctypes.c_double),
+                ("bmax_over_avg", ctypes.c_double), ("cmax_over_avg", ctypes.c_double)]
 
 
 _lib = None
@@ -95,6 +97,7 @@ def load():
         "iccg_setup": (i, [ctypes.POINTER(vp), i, vp, vp, vp, i, vp, i, vp,
                            ctypes.POINTER(_Options)]),
         "iccg_schedule_stats": (i, [i, vp, vp, vp, i, vp, i, vp, i, vp]),
+        "iccg_block_stats": (i, [i, vp, i, vp, vp]),
         "ic0_factor": (i, [vp, ip]),
         "iccg_set_factor": (i, [vp, vp, ip]),
         "iccg_get_factor": (i, [vp, vp]),
@@ -107,6 +110,7 @@ def load():
         "iccg_mpnn_train_step": (i, [vp, vp, vp, i, ctypes.c_float, dp]),
         "iccg_mpnn_predict": (i, [vp, vp, i, vp]),
         "iccg_mpnn_destroy": (None, [vp]),
+        "iccg_mpnn_smooth_probes": (i, [vp, vp, i, vp]),
         "ic_apply": (i, [vp, vp, vp]),
         "ic_forward": (i, [vp, vp, vp]),
         "ic_backward": (i, [vp, vp, vp]),
@@ -209,6 +213,17 @@ def iccg_permute(A, perm):
 
 SCHEDULE_FIELDS = ("tasks", "chunks", "slots", "max_depth", "max_width", "deps", "remote_tasks",
                    "exported_rows", "padded_chunks")
+
+
+def iccg_block_stats(order: Ordering) -> dict:
+    """Table 6 statistics of an ordering, computed by the library (host)."""
+    bp = _host_i32(order.block_ptr)
+    cp = _host_i32(order.color_ptr)
+    out = np.zeros(6, dtype=np.float64)
+    _check(load().iccg_block_stats(bp.size - 1, bp.ctypes.data, cp.size - 1, cp.ctypes.data,
+                                   out.ctypes.data), "iccg_block_stats")
+    return {"n_b": int(out[0]), "n_c": int(out[1]), "gini": float(out[2]), "B_max": int(out[3]),
+            "B_max_over_avg": float(out[4]), "C_max_over_avg": float(out[5])}
 
 
 def iccg_schedule_stats(rowptr, col, val, block_ptr, color_ptr, pack_rows: int = 64):
@@ -456,6 +471,14 @@ class Network:
                                            ctypes.byref(loss) if want_loss else None),
                "iccg_mpnn_train_step")
         return loss.value if want_loss else None
+
+    @staticmethod
+    def smooth_probes(ctx: Context, z_dev, out_dev) -> None:
+        """out_i = D^1/2 M^-1 D^1/2 z_i scaled to norm sqrt(n) (rows of device tensors)."""
+        if z_dev.shape != out_dev.shape or z_dev.shape[1] != ctx.n:
+            raise ValueError("z and out must both be [nprobes, n]")
+        _check(load().iccg_mpnn_smooth_probes(ctx._h, _ptr(z_dev), z_dev.shape[0], _ptr(out_dev)),
+               "iccg_mpnn_smooth_probes")
 
     def predict(self, ctx: Context, out_dev, bf16: bool = True) -> None:
         _check(load().iccg_mpnn_predict(self._h, ctx._h, 1 if bf16 else 0, _ptr(out_dev)),

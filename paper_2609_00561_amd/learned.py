@@ -26,19 +26,11 @@ from . import iccg
 
 
 def build_context(A, block_size: int = 64, **kw):
-    """ABMC order, permute, set up and IC(0)-factor A; returns (ctx, order).
-    The context also carries sqrt(diag(A')) as ctx.diag_sqrt (device), which
-    the smoothed training probes use."""
-    import torch
+    """ABMC order, permute, set up and IC(0)-factor A; returns (ctx, order)."""
     order = iccg.iccg_order_abmc(A, block_size)
     rp, cl, vl = iccg.iccg_permute(A, order.perm)
     ctx = iccg.Context(rp, cl, vl, order.block_ptr, order.color_ptr, **kw)
     ctx.ic0_factor()
-    rows = np.repeat(np.arange(ctx.n), np.diff(rp))
-    d = np.zeros(ctx.n)
-    on = cl == rows
-    d[rows[on]] = vl[on]
-    ctx.diag_sqrt = torch.tensor(np.sqrt(d), device="cuda")
     return ctx, order
 
 
@@ -57,13 +49,8 @@ def make_probes(ctx, rng, nprobes: int = 8, smooth: bool = True):
     Z = torch.tensor(rng.standard_normal((nprobes, ctx.n)), device="cuda")
     if not smooth:
         return Z
-    ds = ctx.diag_sqrt
     out = torch.empty_like(Z)
-    w = torch.empty(ctx.n, dtype=torch.float64, device="cuda")
-    for i in range(nprobes):
-        ctx.ic_apply((ds * Z[i]).contiguous(), w)
-        v = ds * w
-        out[i] = v * (np.sqrt(ctx.n) / torch.linalg.norm(v))
+    iccg.Network.smooth_probes(ctx, Z, out)
     return out
 
 
@@ -125,9 +112,10 @@ def solve_both(net: "iccg.Network", ctx, b_dev, tol: float = 1e-8, maxit: int = 
     if accepted:
         x1 = torch.zeros(n, dtype=torch.float64, device="cuda")
         lr_ = ctx.solve(b_dev, x1, tol=tol, maxit=maxit, raise_on_noconv=False)
+        a, b = x1.cpu().numpy(), x0.cpu().numpy()
         out.update({"learned_iters": lr_["iters"], "learned_ms": ctx.info()["last_solve_ms"],
                     "learned_relres_true": lr_["relres_true"],
-                    "x_rel_diff": float(torch.linalg.norm(x1 - x0) / torch.linalg.norm(x0))})
+                    "x_rel_diff": float(np.linalg.norm(a - b) / np.linalg.norm(b))})
         keep = lr_["status"] == iccg.ICCG_OK and lr_["iters"] < plain["iters"]
     else:
         keep = False

@@ -3,6 +3,11 @@
 Tolerances: the GPU trains in FP32, so the probe loss matches the FP64 oracle
 to 1e-5 relative and every parameter block's gradient to 1e-3 relative
 (norm-wise); the zero-initialized output layer reproduces IC(0) bit for bit.
+Adam steps match the oracle's update rule to FP32 rounding of the parameters
+plus 1e-4 of the step size.  BF16 inference rounds the weights and every
+layer's output once to BF16 (unit roundoff 2^-9): along any path through the
+four layers that is at most 8 roundings to first order, 8 * 2^-9 = 1.6 % of
+the predicted correction; the bar against the FP64 oracle is 5 %.
 """
 import numpy as np
 import pytest
@@ -115,6 +120,111 @@ def test_bf16_inference_close_to_fp32():
     assert np.max(np.abs(a - ref)) <= 1e-5 * np.max(np.abs(ref))
 
 
+def test_adam_steps_match_oracle():
+    """Two iccg_mpnn_train_step calls from a fixed theta, parameters read back
+    after each.  (1) Fed the GPU's own FP32 gradient (iccg_mpnn_loss_grad at the
+    same theta and probes; the gradient kernels are deterministic), the
+    oracle's Adam reproduces the GPU's parameters to FP32 rounding: this pins
+    the update rule, the bias corrections and the moment state carried into
+    the second step.  (2) Fed the FP64 oracle's gradients, the oracle's two
+    steps agree element by element wherever the GPU's gradient matches the
+    oracle's within 5 % (at least 90 % of them); Adam's first step moves every
+    parameter by lr * sign(g), so the others may differ by up to 2 lr per
+    step."""
+    o, csr, Ap, lval, _ = _matrix(6, 21)
+    th0 = _theta(21).astype(np.float32)
+    lr = 1e-3
+    rng = np.random.default_rng(22)
+    Zs = [rng.standard_normal((8, Ap.n)) for _ in range(2)]
+    g = mpnn.Graph(Ap)
+    with _ctx(o, csr) as ctx, iccg.Network(th0) as net:
+        thetas, grads, losses = [th0.astype(np.float64)], [], []
+        for Z in Zs:
+            Zd = torch.tensor(Z, device="cuda")
+            L, G = net.loss_grad(ctx, Zd)
+            Lt = net.train_step(ctx, Zd, lr=lr, want_loss=True)
+            assert Lt == L           # same deterministic forward/backward
+            grads.append(G.astype(np.float64))
+            losses.append(L)
+            thetas.append(net.params().astype(np.float64))
+    # (1) the GPU's gradients through the oracle's Adam
+    m = np.zeros(th0.size)
+    v = np.zeros(th0.size)
+    for step in (1, 2):
+        want, m, v = mpnn.adam(thetas[step - 1], grads[step - 1], m, v, step, lr=lr)
+        got = thetas[step]
+        tol = 4 * 2.0 ** -24 * np.abs(want) + 1e-4 * lr
+        bad = np.abs(got - want) > tol
+        print("step", step, "max |d theta| vs oracle Adam on the GPU gradient",
+              np.max(np.abs(got - want)), "violations", int(bad.sum()))
+        assert not bad.any()
+    # (2) the FP64 oracle's gradients and Adam from the same theta
+    th = th0.astype(np.float64)
+    m = np.zeros(th.size)
+    v = np.zeros(th.size)
+    firm = np.ones(th.size, dtype=bool)
+    for step, Z in ((1, Zs[0]), (2, Zs[1])):
+        Lr, Gr = mpnn.loss_and_grad(th, Ap, lval, g, Z)
+        if step == 1:
+            assert losses[0] == pytest.approx(Lr, rel=1e-5)
+        # an element is firm when the GPU's gradient (at the GPU's theta) is
+        # within 5 % of the oracle's at every step: then Adam's update differs
+        # by at most about 0.07 lr
+        firm &= np.abs(grads[step - 1] - Gr) <= 0.05 * np.abs(Gr)
+        th, m, v = mpnn.adam(th, Gr, m, v, step, lr=lr)
+    d = np.abs(thetas[2] - th)
+    print("oracle-gradient Adam: firm elements", int(firm.sum()), "of", th.size,
+          "max diff firm", float(d[firm].max()), "max diff all", float(d.max()))
+    assert firm.sum() >= 0.9 * th.size
+    assert np.all(d[firm] <= 4 * 2.0 ** -24 * np.abs(th[firm]) + 0.1 * lr)
+    # Adam moves each parameter by at most a few lr per step
+    assert np.all(d <= 4 * lr + 4 * 2.0 ** -24 * np.abs(th))
+
+
+def test_bf16_inference_vs_fp64_oracle():
+    """BF16 inference (the production path) against the FP64 network oracle:
+    the predicted correction within 5 % (norm-wise), and no factor entry
+    farther from the oracle's than 5 % of the largest correction."""
+    for m_, seed in ((8, 31), (10, 32)):
+        o, csr, Ap, lval, _ = _matrix(m_, seed)
+        th = _theta(seed + 1).astype(np.float32)
+        with _ctx(o, csr) as ctx, iccg.Network(th) as net:
+            lv = torch.zeros(Ap.nnz, dtype=torch.float64, device="cuda")
+            net.predict(ctx, lv, bf16=True)
+            got = lv.cpu().numpy()
+        g = mpnn.Graph(Ap)
+        lt, cache = mpnn.forward(th.astype(np.float64), Ap, lval, g)
+        ref = mpnn.factor_from_scaled(g, lt, cache["s"])
+        lower = g.lower
+        corr_ref = ref[lower] - lval[lower]
+        corr_got = got[lower] - lval[lower]
+        rel = np.linalg.norm(corr_got - corr_ref) / np.linalg.norm(corr_ref)
+        fac = np.max(np.abs(got - ref)) / np.max(np.abs(corr_ref))
+        print(m_, seed, "bf16 correction rel err vs fp64 oracle", rel,
+              "largest factor error / largest correction", fac)
+        assert rel <= 0.05
+        assert fac <= 0.05
+
+
+def test_smoothed_probes_vs_oracle():
+    """iccg_mpnn_smooth_probes: D^1/2 M0^-1 D^1/2 z scaled to norm sqrt(n),
+    against the same steps on the host with the oracle's IC(0) application."""
+    o, csr, Ap, lval, _ = _matrix(8, 41)
+    Z = np.random.default_rng(42).standard_normal((3, Ap.n))
+    with _ctx(o, csr) as ctx:
+        out = torch.empty(3, Ap.n, dtype=torch.float64, device="cuda")
+        iccg.Network.smooth_probes(ctx, torch.tensor(Z, device="cuda"), out)
+        got = out.cpu().numpy()
+    d = np.sqrt(Ap.val[[k for i in range(Ap.n) for k in range(Ap.rowptr[i], Ap.rowptr[i + 1])
+                        if Ap.col[k] == i]])
+    for i in range(3):
+        v = d * oracle.ic_apply(Ap, lval, d * Z[i])
+        want = v * (np.sqrt(Ap.n) / np.linalg.norm(v))
+        err = np.max(np.abs(got[i] - want)) / np.max(np.abs(want))
+        assert err <= 1e-12, (i, err)
+        assert np.linalg.norm(got[i]) == pytest.approx(np.sqrt(Ap.n), rel=1e-13)
+
+
 def test_training_reduces_probe_loss():
     mats = [_matrix(8, s) for s in range(3)]
     th = synth.glorot_params(iccg.mpnn_param_shapes(), 11).astype(np.float32)
@@ -157,25 +267,44 @@ def test_negative_pivot_falls_back():
 
 
 def test_trained_network_on_unseen_matrices():
-    """Train on seeded 32^3 lognormal matrices, then compare learned and plain
-    IC(0) on unseen seeds.  The printed gains are reported, not pinned (no
-    paper number exists); the fallback rule is pinned: the factor kept never
-    needs more iterations than plain IC(0)."""
+    """Train on seeded 32^3 lognormal matrices, then measure what the trained
+    network gains over plain IC(0) on unseen seeds, one per sigma in
+    {0.5, 1, 2}: the probe loss (the training objective,
+    ||L~ L~^T z - A~ z||^2 / ||A~ z||^2 over smoothed probes) against that of
+    plain IC(0) (the same network with its zero output layer), and the raw CG
+    iteration counts with the learned factor against plain IC(0).
+
+    Observed (printed): the gain is small.  The learned factor saves about one
+    iteration in 150-250 (0.5 %), and the probe loss moves by about 1 % either
+    way; there is no paper number for this form.  Asserted: the learned factor
+    never costs more than max(2, 2 %) extra iterations on an unseen matrix, and
+    the fallback rule: the factor kept never needs more iterations than plain
+    IC(0), and the context keeps it for later solves."""
     from paper_2609_00561_amd import learned
     train_ctxs = [learned.build_context(synth.workload("lognormal7_32", k)[0], 64)[0]
                   for k in range(16)]
-    with iccg.Network(learned.init_params(0)) as net:
+    rng = np.random.default_rng(5)
+    with iccg.Network(learned.init_params(0)) as net, \
+            iccg.Network(learned.init_params(0)) as plain_net:
         hist = learned.train(net, train_ctxs, epochs=6, lr=1e-3, seed=1)
         for c in train_ctxs:
             c.close()
         print("probe loss by epoch", hist)
         assert hist[-1] < hist[0]
-        for seed in (10000, 10001, 10002):
-            A, b = synth.workload("lognormal7_32", seed)
+        for seed, sigma in ((10000, 0.5), (10001, 1.0), (10002, 2.0)):
+            A = synth.grid3d_7pt_lognormal(32, 32, 32, sigma, 1e-6, np.random.default_rng(seed))
+            b = synth.uniform_rhs(A.n, np.random.default_rng(seed + 1))
             ctx, order = learned.build_context(A, 64)
             with ctx:
+                Z = learned.make_probes(ctx, rng, 8)
+                l_trained = net.loss_grad(ctx, Z)[0]
+                l_plain = plain_net.loss_grad(ctx, Z)[0]
                 ev = learned.solve_both(net, ctx, torch.tensor(b[order.perm], device="cuda"))
-                print("unseen seed", seed, ev)
+                print(f"unseen seed {seed} sigma {sigma}: probe loss {l_plain:.5f} -> {l_trained:.5f}; "
+                      f"iterations plain {ev['plain_iters']} learned {ev.get('learned_iters')} "
+                      f"kept {ev['kept']}")
+                assert ev["pivot_ok"]
+                assert ev["learned_iters"] <= ev["plain_iters"] + max(2, int(0.02 * ev["plain_iters"]))
                 kept_iters = ev["learned_iters"] if ev["kept"] == "learned" else ev["plain_iters"]
                 assert kept_iters <= ev["plain_iters"]
                 # after the choice the context holds the kept factor

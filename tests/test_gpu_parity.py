@@ -7,14 +7,20 @@ Tolerances:
   FMA, so every row differs by a few ulps at most).
 * SpMV: 1e-14 relative per entry scale; dot products 1e-13 relative.
 * Solve: relres <= tol, iteration count within max(2, 1%) of the oracle's,
-  residual histories within 1e-6 relative over the first 20 iterations and
-  1e-2 over the first 50 while the residual is above 1e-6 of its peak
-  (rounding noise grows with the condition number and with transient residual
-  growth).
+  residual histories within 1e-6 relative over the first min(50, k) + 1
+  entries, and ||x - x_o|| / ||x_o|| within its 2-norm and energy-norm bounds
+  (the smallest eigenvalue of A, and the Lanczos estimate of kappa(M^-1 A)
+  from the oracle's CG coefficients; see _parity_util).  Where the history
+  is farther than 1e-6 from the oracle's, it must stay within 10 times the
+  distance by which the oracle's own history moves when b changes by one ulp
+  (measured: 0.5-0.6 on the 27-point sigma = 2 stencil on 12^3, whose
+  residual grows 100-fold before it falls; 0.4-3e-6 under node-level
+  multicoloring of the 7-point 16^3 matrix; 1e-9 or less elsewhere).
 """
 import numpy as np
 import pytest
 
+import _parity_util as pu
 import oracle
 import synth
 
@@ -185,18 +191,20 @@ def test_solve_parity(case):
     assert res["relres"] <= 1e-8
     assert res["relres_true"] <= 1e-7
     assert abs(res["iters"] - ref.iters) <= max(2, int(0.01 * ref.iters))
-    # rounding differences grow with the condition number; the early history
-    # must agree tightly, the later one loosely
-    m = min(20, ref.iters, res["iters"]) + 1
-    assert np.allclose(hist[:m], ref.history[:m], rtol=1e-6, atol=0)
     m = min(50, ref.iters, res["iters"]) + 1
-    above = ref.history[:m] >= 1e-6 * np.max(ref.history)
-    assert np.allclose(hist[:m][above], ref.history[:m][above], rtol=1e-2, atol=0)
-    err = np.linalg.norm(x - ref.x) / np.linalg.norm(ref.x)
-    print(case, "iters", res["iters"], ref.iters, "x rel diff", err)
-    # the two iterates both satisfy relres <= 1e-8; their distance is bounded
-    # by kappa-scaled residuals, so only a loose check here
-    assert err <= 1e-3
+    dev = pu.history_deviation(hist, ref.history, m)
+    rep = pu.solution_report(cs[4], cs[5], cs[6], x, ref, pu.lambda_min_lower(cs[0], case[0]), 1e-8)
+    print(case, "iters", res["iters"], ref.iters, "history deviation", dev, rep)
+    if dev > 1e-6:
+        sens = pu.history_sensitivity(cs[4], cs[5], cs[6], 1e-8, m)
+        print(case, "oracle history sensitivity to one ulp of b", sens)
+        assert dev <= 10.0 * sens
+    # both iterates satisfy relres <= 1e-8; their distance is bounded by the
+    # residuals scaled by the conditioning
+    assert rep["err2"] <= 2.0 * rep["bound2"]
+    assert rep["errA"] <= 2.0 * rep["boundA"]
+    # the target: the oracle's solution to 1e-8 relative (measured <= 3e-11)
+    assert rep["err2"] <= 1e-8
 
 
 def test_solve_matches_oracle_to_1e8_when_tight():
@@ -205,7 +213,11 @@ def test_solve_matches_oracle_to_1e8_when_tight():
     cs = _case("laplace2d_64", "abmc", 64)
     ref, res, hist, x = _solve_both(cs, 1e-12, 5000)
     assert res["status"] == iccg.ICCG_OK
-    assert np.linalg.norm(x - ref.x) / np.linalg.norm(ref.x) <= 1e-8
+    rep = pu.solution_report(cs[4], cs[5], cs[6], x, ref, pu.lambda_min_lower(cs[0], "laplace2d_64"),
+                             1e-12)
+    print("laplace2d_64 at 1e-12:", rep)
+    assert rep["bound2"] <= 1e-8          # the bound permits the 1e-8 claim ...
+    assert rep["err2"] <= 1e-8            # ... and the solutions meet it
 
 
 def test_graph_and_eager_identical():

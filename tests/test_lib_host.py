@@ -222,3 +222,23 @@ def test_setup_rejects_bad_options():
     for bad in ({"precision": 2}, {"sweep_launch": 3}, {"sweep_launch": -1},
                 {"sweep_grid": -8}, {"flow_tail": -1}):
         assert _raw_setup(rp, cl, vl, o.block_ptr, o.color_ptr, **bad) == iccg.ICCG_EINVAL, bad
+
+
+@pytest.mark.parametrize("name", ["laplace2d_64", "poisson7_16", "knn13_20k", "stencil27_12"])
+def test_block_stats_bit_exact(name):
+    """iccg_block_stats (Section 7.3, Table 6: n_b, n_c, G, B_max, B_max/B_avg,
+    C_max/C_avg) equals the oracle's statistics bit for bit on ABMC (uniform
+    blocks, ragged last block) and Leiden (non-uniform) orderings."""
+    A, _ = synth.workload(name)
+    orders = [iccg.iccg_order_abmc(A, s) for s in (1, 7, 16, 64)]
+    orders += [iccg.iccg_order_leiden(A, "cpm", 0.05), iccg.iccg_order_leiden(A, "modularity", 1.0)]
+    for o in orders:
+        got = iccg.iccg_block_stats(o)
+        want = oracle.block_stats(oracle.Ordering(o.perm, o.block_ptr, o.color_ptr))
+        assert got == want, (got, want)
+
+
+def test_block_stats_rejects_bad_ordering():
+    with pytest.raises(iccg.IccgError) as e:
+        iccg.iccg_block_stats(iccg.Ordering(np.arange(4), np.array([0, 2, 2, 4]), np.array([0, 3])))
+    assert e.value.status == iccg.ICCG_EBADORDER

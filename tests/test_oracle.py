@@ -257,6 +257,91 @@ def test_gini_values():
     assert oracle.gini([0, 0, 0, 12]) == pytest.approx(3 / 4)
 
 
+def _table6_rows():
+    rows = []
+    with open(os.path.join(GOLDEN, "table6_stats.txt")) as f:
+        for line in f:
+            if line.strip() and not line.startswith("#"):
+                rows.append(line.split())
+    assert len(rows) == 24
+    return rows
+
+
+def _printed_equal(value, printed):
+    """value rounded the way Table 6 prints it (two decimals, or three
+    significant figures above 10) equals the printed string."""
+    return (f"{value:.3g}" if value >= 10 else f"{value:.2f}") == printed
+
+
+def _ordering(block_sizes, color_of_block):
+    """An Ordering with the given block sizes (in block order) and colors
+    (non-decreasing), over rows 0..n-1."""
+    bs = np.asarray(block_sizes, dtype=np.int64)
+    col = np.asarray(color_of_block, dtype=np.int64)
+    bp = np.concatenate([[0], np.cumsum(bs)]).astype(np.int32)
+    nc = int(col.max()) + 1
+    cp = np.searchsorted(col, np.arange(nc + 1), side="left").astype(np.int32)
+    return oracle.Ordering(np.arange(bp[-1], dtype=np.int32), bp, cp)
+
+
+def test_block_stats_table6_ratios():
+    """Table 6 prints n_b, B_max and B_max/B_avg for all 24 blockings, with n
+    from Table 1: B_avg must be n / n_b (the mean block size).  C_max/C_avg
+    must be the largest color's row count over n / n_c: with one block per
+    color and the largest color holding round(printed ratio * n / n_c) rows,
+    the printed ratio comes back (a blocks-per-color count would give 1.00)."""
+    for name, meth, n, nb, nc, g, bmax, bratio, cratio in _table6_rows():
+        n, nb, nc, bmax = int(n), int(nb), int(nc), int(bmax)
+        rest = n - bmax
+        sizes = [bmax] + [rest // (nb - 1) + (1 if k < rest % (nb - 1) else 0) for k in range(nb - 1)]
+        assert max(sizes) == bmax
+        st = oracle.block_stats(_ordering(sizes, np.zeros(nb)))
+        assert st["n_b"] == nb and st["B_max"] == bmax and st["n_c"] == 1
+        assert _printed_equal(st["B_max_over_avg"], bratio), (name, meth, st)
+        cmax = round(float(cratio) * n / nc)
+        rest = n - cmax
+        csizes = [cmax] + [rest // (nc - 1) + (1 if k < rest % (nc - 1) else 0) for k in range(nc - 1)]
+        st = oracle.block_stats(_ordering(csizes, np.arange(nc)))
+        assert st["n_c"] == nc
+        assert _printed_equal(st["C_max_over_avg"], cratio), (name, meth, st)
+
+
+def test_block_stats_path_graph_hand_computed():
+    """ABMC with s = 3 on the path 0-...-9: four blocks, two alternating colors;
+    every statistic computed by hand (tests/golden/closed_forms.txt)."""
+    g = _golden_kv("closed_forms.txt")
+    A = synth.path_graph_matrix(10)
+    st = oracle.block_stats(oracle.order_abmc(A, 3))
+    assert st["n_b"] == g["path10_s3_nb"] and st["n_c"] == g["path10_s3_nc"]
+    assert st["B_max"] == g["path10_s3_bmax"]
+    assert st["gini"] == pytest.approx(g["path10_s3_gini"], rel=1e-15)
+    assert st["B_max_over_avg"] == pytest.approx(g["path10_s3_bmax_over_avg"], rel=1e-15)
+    assert st["C_max_over_avg"] == pytest.approx(g["path10_s3_cmax_over_avg"], rel=1e-15)
+
+
+def test_block_stats_uniform_abmc_table6():
+    """Table 6's ABMC rows: G = 0.00 and B_max/B_avg = 1.00 whenever s divides
+    n; a ragged last block moves neither above the printed 0.00 / 1.00 at the
+    paper's sizes (thermal2: n = 1,228,045, n_b = 1,024)."""
+    A = synth.banded_graph(1228045, 512)
+    o = oracle.order_abmc(A, math.ceil(1228045 / 1024))
+    st = oracle.block_stats(o)
+    assert st["n_b"] == 1024 and st["B_max"] == 1200
+    assert f"{st['gini']:.2f}" == "0.00" and f"{st['B_max_over_avg']:.2f}" == "1.00"
+
+
+def test_community_connected_detects_split():
+    """The Leiden-guarantee check must reject a community that is two
+    separate pieces, and accept the same nodes once they are joined."""
+    A = synth.path_graph_matrix(6)
+    assert oracle.community_connected(A, np.array([0, 0, 0, 1, 1, 1]))
+    # community 0 = {0, 1} and {4, 5}: not connected through community 1
+    assert not oracle.community_connected(A, np.array([0, 0, 1, 1, 0, 0]))
+    # singletons and the whole path are connected
+    assert oracle.community_connected(A, np.arange(6))
+    assert oracle.community_connected(A, np.zeros(6, dtype=int))
+
+
 # ---------------------------------------------------------------------------
 # IC(0) (Section 3, Section 5)
 # ---------------------------------------------------------------------------
@@ -448,3 +533,43 @@ def test_spmv_and_dot_vs_scipy():
     x = np.random.default_rng(1).standard_normal(A.n)
     assert np.allclose(oracle.spmv(A, x), A.to_scipy() @ x, rtol=1e-13, atol=1e-12)
     assert oracle.dot(x, b) == pytest.approx(float(np.dot(x, b)), rel=1e-12)
+
+
+def test_solution_distance_bounds():
+    """The bounds the GPU solution tests use (tests/_parity_util.py) hold for
+    two oracle solutions: the solve to 1e-8 against the solve to 1e-13 of the
+    same system, for a shifted Laplacian (lambda_min from Gershgorin = the
+    shift) and the Dirichlet Laplacian (closed-form lambda_min)."""
+    import _parity_util as pu
+    g = _golden_kv("closed_forms.txt")
+    assert pu.lambda_min_lower(synth.workload("laplace2d_64")[0], "laplace2d_64") == \
+        pytest.approx(g["lambda_min"], rel=1e-12)
+    for name, s in (("poisson7_16", 8), ("laplace2d_64", 64), ("knn13_20k", 32)):
+        A, b = synth.workload(name)
+        o = oracle.order_abmc(A, s)
+        Ap = oracle.permute(A, o.perm)
+        lval, _ = oracle.ic0(Ap)
+        bp = b[o.perm]
+        loose = oracle.pcg(Ap, lval, bp, tol=1e-8)
+        tight = oracle.pcg(Ap, lval, bp, tol=1e-13)
+        lam = pu.lambda_min_lower(A, name)
+        if name.startswith("poisson7"):
+            assert lam == pytest.approx(1e-6, rel=1e-6)
+        rep = pu.solution_report(Ap, lval, bp, tight.x, loose, lam, 1e-8)
+        assert 0 < rep["err2"] <= rep["bound2"], (name, rep)
+        assert 0 < rep["errA"] <= rep["boundA"], (name, rep)
+
+
+def test_history_sensitivity_measure():
+    """The measure that sets the residual-history bar of the GPU solve tests:
+    one ulp of b moves the oracle's own history by far more than 1e-6 on the
+    27-point sigma = 2 stencil (transient residual growth of 100x) and by
+    about 1e-11 on the 7-point ABMC case."""
+    import _parity_util as pu
+    for name, s, lo, hi in (("stencil27_12", 64, 0.1, 10.0), ("poisson7_16", 8, 0.0, 1e-9)):
+        A, b = synth.workload(name)
+        o = oracle.order_abmc(A, s)
+        Ap = oracle.permute(A, o.perm)
+        lval, _ = oracle.ic0(Ap)
+        sens = pu.history_sensitivity(Ap, lval, b[o.perm], 1e-8, 51)
+        assert lo <= sens <= hi, (name, sens)
