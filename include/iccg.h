@@ -211,6 +211,21 @@ int ic_backward(iccg_ctx *c, const double *y, double *z);
 /* q = A' p (the CG step's SpMV); *pq_host (may be NULL) receives (p, q). DEVICE p, q. */
 int iccg_spmv(iccg_ctx *c, const double *p, double *q, double *pq_host);
 
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): iccg_spmv
+ * with the dot product left on the device.  q = A'p and *pq_dev = (p, q)
+ * (DEVICE p, q of n; pq_dev: one DEVICE double), enqueued on the context's
+ * stream with no host synchronization; results equal iccg_spmv's bit for bit.
+ * The per-workgroup partial sums live in a library-wide static device array of
+ * 2^17 doubles (1 MiB per GPU, held until the process ends), so the call
+ * allocates nothing; every partial is rewritten before it is read, so nothing
+ * needs clearing.  All calls on one GPU share that array: calls that overlap
+ * on one GPU (other streams, other threads) race.  ICCG_EINVAL for n > 2^24
+ * rows, for null or equal p and q, or a null pq_dev.
+ */
+int iccg_spmv_dot_noalloc(iccg_ctx *c, const double *p, double *q, double *pq_dev);
+
 /* *out_host = (a, b), deterministic two-pass FP64 reduction.  DEVICE a, b of n. */
 int iccg_dot(iccg_ctx *c, const double *a, const double *b, double *out_host);
 

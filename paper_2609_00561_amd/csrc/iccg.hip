@@ -33,6 +33,7 @@
 #include <cmath>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <string>
 #include <type_traits>
@@ -988,7 +989,42 @@ __global__ __launch_bounds__(64) void k_sweep_flow(const TaskRec *__restrict__ t
     }
 }
 
+// ---------------------------------------------------------------------------
+// static scratch of the allocation-free entry point (iccg_spmv_dot_noalloc)
+// ---------------------------------------------------------------------------
+// The SpMV's per-workgroup partial sums, one double per workgroup: 2^17 of
+// them cover n <= 2^24 rows.  Each GPU holds its own copy for the life of the
+// process; host code reaches it only through the address hipGetSymbolAddress
+// returns for the current device (resolved in iccg_setup), never through the
+// array's name.
+constexpr int kNoAllocParts = 1 << 17;
+__device__ __align__(256) double scratch[kNoAllocParts];
+
 namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on device dev (the current device), resolved
+// once per device.
+int resolve_scratch(int dev) {
+    if (dev < 0 || dev >= kMaxDevices) return set_error(ICCG_EINVAL, "device index out of range");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[dev]) return ICCG_OK;
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+        return set_error(ICCG_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_ptr[dev] = static_cast<double *>(ptr);
+    return ICCG_OK;
+}
+
+double *scratch_for(int dev) {
+    if (dev < 0 || dev >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    return g_scratch_ptr[dev];
+}
 
 int grid_for(long long items, int threads, int cap) {
     long long g = (items + threads - 1) / threads;
@@ -997,11 +1033,14 @@ int grid_for(long long items, int threads, int cap) {
     return static_cast<int>(g);
 }
 
+// part: one partial sum per workgroup (c->spmv_blocks of them); NULL = the
+// context's partial buffer
 int launch_spmv(iccg_ctx *c, int mode, const double *x, double *y, const double *b,
-                const DevScalars *sc) {
+                const DevScalars *sc, double *part = nullptr) {
     dim3 grid(c->spmv_blocks), block(64);
+    if (!part) part = c->part.p;
     if (c->prof) c->prof->begin(c->work);
-#define SPMV_ARGS c->n, c->nslices, c->sell_rec.p, c->sell_col.p, c->sell_val.p, x, y, b, c->part.p, sc
+#define SPMV_ARGS c->n, c->nslices, c->sell_rec.p, c->sell_col.p, c->sell_val.p, x, y, b, part, sc
 #define SPMV_W(M)                                                                              \
     switch (c->sell_wmax) {                                                                    \
         case 8: hipLaunchKernelGGL((k_spmv<M, 8>), grid, block, 0, c->work, SPMV_ARGS); break;   \
@@ -1738,6 +1777,8 @@ int iccg_setup(iccg_ctx **out, int n, const int *rowptr, const int *col, const d
         HIP_CHECK(hipStreamCreateWithFlags(&c->work, hipStreamNonBlocking));
         int dev = 0;
         HIP_CHECK(hipGetDevice(&dev));
+        c->device = dev;
+        ICCG_CHECK(resolve_scratch(dev));
         HIP_CHECK(hipDeviceGetAttribute(&c->num_cu, hipDeviceAttributeMultiprocessorCount, dev));
         HIP_CHECK(hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming));
         HIP_CHECK(hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming));
@@ -1882,6 +1923,22 @@ int iccg_spmv(iccg_ctx *c, const double *p, double *q, double *pq_host) {
             HIP_CHECK(hipMemcpyAsync(pq_host, c->b.p, sizeof(double), hipMemcpyDeviceToHost, c->work));
             HIP_CHECK(hipStreamSynchronize(c->work));
         }
+        return ICCG_OK;
+    });
+}
+
+int iccg_spmv_dot_noalloc(iccg_ctx *c, const double *p, double *q, double *pq_dev) {
+    return entry(c, [&]() -> int {
+        if (!p || !q || !pq_dev || p == q) return set_error(ICCG_EINVAL, "need distinct p, q and a device pq");
+        if (c->spmv_blocks > kNoAllocParts)
+            return set_error(ICCG_EINVAL, "iccg_spmv_dot_noalloc: n = " + std::to_string(c->n) +
+                                              " exceeds the static scratch (at most 2^24 rows)");
+        double *part = scratch_for(c->device);
+        if (!part) return set_error(ICCG_ESTATE, "static scratch not resolved for this device");
+        ICCG_CHECK(launch_spmv(c, SP_PLAIN, p, q, nullptr, nullptr, part));
+        hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kReduceThreads), 0, c->work, part, c->spmv_blocks,
+                           c->scal.p, OP_STORE, pq_dev, c->hist.p);
+        HIP_CHECK(hipGetLastError());
         return ICCG_OK;
     });
 }

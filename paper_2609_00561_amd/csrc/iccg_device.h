@@ -204,6 +204,7 @@ struct iccg_ctx {
     int graph_iters = 0;
     long long flow_sweeps = 0;    // single-launch sweeps since the flags were last cleared
     int num_cu = 0;                 // compute units of the device
+    int device = 0;                 // HIP device current at iccg_setup
     int last_resident = 0;          // workgroups of the last single-launch sweep
     int flow_tail = 0;              // hybrid sweeps: first color of the dataflow part
     std::unordered_map<const void *, int> resident;   // resident workgroups per CU, per kernel

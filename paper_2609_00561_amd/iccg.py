@@ -44,7 +44,7 @@ EXPORTS = [
     "iccg_strerror", "iccg_last_error",
     "iccg_destroy", "iccg_mpnn_param_count", "iccg_mpnn_create", "iccg_mpnn_get_params",
     "iccg_mpnn_set_params", "iccg_mpnn_loss_grad", "iccg_mpnn_train_step", "iccg_mpnn_predict",
-    "iccg_mpnn_destroy", "iccg_mpnn_smooth_probes",
+    "iccg_mpnn_destroy", "iccg_mpnn_smooth_probes", "iccg_spmv_dot_noalloc",
 ]
 
 
@@ -115,6 +115,7 @@ def load():
         "ic_forward": (i, [vp, vp, vp]),
         "ic_backward": (i, [vp, vp, vp]),
         "iccg_spmv": (i, [vp, vp, vp, dp]),
+        "iccg_spmv_dot_noalloc": (i, [vp, vp, vp, vp]),
         "iccg_dot": (i, [vp, vp, vp, dp]),
         "iccg_solve": (i, [vp, vp, vp, d, i, ip, dp, dp]),
         "iccg_residual_history": (i, [vp, vp, i]),
@@ -336,6 +337,11 @@ class Context:
         _check(load().iccg_spmv(self._h, _ptr(p), _ptr(q), ctypes.byref(pq) if want_dot else None),
                "iccg_spmv")
         return pq.value if want_dot else None
+
+    def spmv_dot_noalloc(self, p, q, pq_dev) -> None:
+        """q = A'p and pq_dev[0] = (p, q) on the device; allocates nothing."""
+        _check(load().iccg_spmv_dot_noalloc(self._h, _ptr(p), _ptr(q), _ptr(pq_dev)),
+               "iccg_spmv_dot_noalloc")
 
     def dot(self, a, b) -> float:
         out = ctypes.c_double(0.0)
