@@ -545,68 +545,92 @@ __device__ __forceinline__ float lane_pull(float v, int src) {
     return __builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute(src, __builtin_bit_cast(int, v)));
 }
 
-template <typename F, bool FWD, int KMAX, int MODE, typename TIn, typename TOut, class Wait = NoWait,
-          class Mem = PlainMem>
-__device__ __forceinline__ void sweep_chunk(const Chunk &ch, const uint32_t *__restrict__ meta,
-                                            const int *__restrict__ scol,
-                                            const F *__restrict__ sval,
-                                            const F *__restrict__ inv,
-                                            const TIn *__restrict__ in, TOut *__restrict__ out,
-                                            const CgArgs &cg, double alpha, F *ys, double &dacc,
-                                            const Wait &wait, const Mem &mem, F &y_out,
-                                            uint32_t &m_out, bool stream) {
+// What one lane holds for one row of a chunk between the load phase (the
+// chunk's schedule: every load that does not depend on other rows' results
+// or on the CG vectors) and the finish phase.  vv/cc first hold the entries
+// of the row at sorted position t (jagged chunks); the finish phase pulls
+// them across to the lanes of their rows.
+template <typename F, int KMAX>
+struct RowRegs {
+    F vv[KMAX];
+    int cc[KMAX];
+    uint32_t m;
+    F dinv;
+};
+
+// Load phase of a chunk: every independent load at once, so they overlap.  A
+// large launch streams its schedule through once (non-temporal: it should
+// not push the gathered values out of L2); a small one reads it normally, so
+// it can stay cached between sweeps.
+template <typename F, int KMAX>
+__device__ __forceinline__ void sweep_load(const Chunk &ch, const uint32_t *__restrict__ meta,
+                                           const int *__restrict__ scol, const F *__restrict__ sval,
+                                           const F *__restrict__ inv, bool stream, RowRegs<F, KMAX> &R) {
+    const int t = static_cast<int>(threadIdx.x) & (kChunkRows - 1);
+    const int nr = ch.shape & 0xffff, W = ch.shape >> 16;
+    const bool jagged = W <= kJaggedMaxWidth;
+    const int i = ch.row0 + t;
+    R.m = 0;
+    R.dinv = F(0);
+    if (t < nr) {
+        int sk = ch.off + t;
+        if (stream) {
+#pragma unroll
+            for (int k = 0; k < KMAX; ++k)
+                if (k < W) {
+                    const int rows_k = slot_rows(ch, k, jagged, nr);
+                    R.vv[k] = F(0);
+                    R.cc[k] = -1;
+                    if (t < rows_k) {
+                        R.vv[k] = __builtin_nontemporal_load(sval + sk);
+                        R.cc[k] = __builtin_nontemporal_load(scol + sk);
+                    }
+                    sk += rows_k;
+                }
+            R.m = __builtin_nontemporal_load(meta + i);
+            R.dinv = __builtin_nontemporal_load(inv + i);
+        } else {
+#pragma unroll
+            for (int k = 0; k < KMAX; ++k)
+                if (k < W) {
+                    const int rows_k = slot_rows(ch, k, jagged, nr);
+                    R.vv[k] = F(0);
+                    R.cc[k] = -1;
+                    if (t < rows_k) {
+                        R.vv[k] = sval[sk];
+                        R.cc[k] = scol[sk];
+                    }
+                    sk += rows_k;
+                }
+            R.m = meta[i];
+            R.dinv = inv[i];
+        }
+    }
+}
+
+// Finish phase of a chunk: the row's right-hand side (for the forward CG
+// sweep r -= alpha q first), the pull of the jagged slots to their rows, the
+// gathers of values final before the chunk (after `wait` has seen their
+// producers), the in-chunk levels through LDS, and the store.
+template <typename F, bool FWD, int KMAX, int MODE, typename TIn, typename TOut, class Wait,
+          class Mem>
+__device__ __forceinline__ void sweep_finish(const Chunk &ch, RowRegs<F, KMAX> &R,
+                                             const int *__restrict__ scol,
+                                             const F *__restrict__ sval,
+                                             const TIn *__restrict__ in, TOut *__restrict__ out,
+                                             const CgArgs &cg, double alpha, F *ys, double &dacc,
+                                             const Wait &wait, int pre, const Mem &mem, F &y_out,
+                                             uint32_t &m_out) {
     const int t = static_cast<int>(threadIdx.x) & (kChunkRows - 1);
     const int nr = ch.shape & 0xffff, W = ch.shape >> 16;
     const bool jagged = W <= kJaggedMaxWidth;
     const bool active = t < nr;
     const int i = ch.row0 + t;
     const int base = ch.off + t;
-    // vv/cc first hold the entries of the row at sorted position t and are
-    // then pulled across to the lanes of their rows (jagged chunks)
-    F vv[KMAX];
-    int cc[KMAX];
-    uint32_t m = 0;
-    F s = F(0), dinv = F(0);
+    const uint32_t m = R.m;
+    F s = F(0);
     double rd = 0.0;
-    // the first dependency a lane waits for, ahead of the chunk's loads
-    const int pre = wait.pre();
     if (active) {
-        // every independent load of the chunk first, so they overlap.  A large
-        // launch streams its schedule through once (non-temporal: it should
-        // not push the gathered values out of L2); a small one reads it
-        // normally, so it can stay cached between sweeps.
-        int sk = base;
-        if (stream) {
-#pragma unroll
-            for (int k = 0; k < KMAX; ++k)
-                if (k < W) {
-                    const int rows_k = slot_rows(ch, k, jagged, nr);
-                    vv[k] = F(0);
-                    cc[k] = -1;
-                    if (t < rows_k) {
-                        vv[k] = __builtin_nontemporal_load(sval + sk);
-                        cc[k] = __builtin_nontemporal_load(scol + sk);
-                    }
-                    sk += rows_k;
-                }
-            m = __builtin_nontemporal_load(meta + i);
-            dinv = __builtin_nontemporal_load(inv + i);
-        } else {
-#pragma unroll
-            for (int k = 0; k < KMAX; ++k)
-                if (k < W) {
-                    const int rows_k = slot_rows(ch, k, jagged, nr);
-                    vv[k] = F(0);
-                    cc[k] = -1;
-                    if (t < rows_k) {
-                        vv[k] = sval[sk];
-                        cc[k] = scol[sk];
-                    }
-                    sk += rows_k;
-                }
-            m = meta[i];
-            dinv = inv[i];
-        }
         if (MODE == SW_CG_FWD) {
             const double ri = cg.r[i] - alpha * cg.q[i];
             cg.r[i] = ri;
@@ -623,8 +647,8 @@ __device__ __forceinline__ void sweep_chunk(const Chunk &ch, const uint32_t *__r
 #pragma unroll
         for (int k = 0; k < KMAX; ++k)
             if (k < W) {
-                vv[k] = lane_pull(vv[k], src);
-                cc[k] = __builtin_amdgcn_ds_bpermute(src, cc[k]);
+                R.vv[k] = lane_pull(R.vv[k], src);
+                R.cc[k] = __builtin_amdgcn_ds_bpermute(src, R.cc[k]);
             }
     }
     // values of other tasks are read only after their producers published them
@@ -636,10 +660,10 @@ __device__ __forceinline__ void sweep_chunk(const Chunk &ch, const uint32_t *__r
         F g[KMAX];
 #pragma unroll
         for (int k = 0; k < KMAX; ++k)
-            if (k < W) g[k] = static_cast<F>(mem.gather(out, cc[k] < 0 ? 0 : cc[k]));
+            if (k < W) g[k] = static_cast<F>(mem.gather(out, R.cc[k] < 0 ? 0 : R.cc[k]));
 #pragma unroll
         for (int k = 0; k < KMAX; ++k)
-            if (k < W) s = (k < ne) ? s - vv[k] * g[k] : s;
+            if (k < W) s = (k < ne) ? s - R.vv[k] * g[k] : s;
         for (int k = KMAX; k < ne; ++k) {
             const int sl = base + k * nr;
             s -= sval[sl] * static_cast<F>(mem.gather(out, scol[sl]));
@@ -649,12 +673,12 @@ __device__ __forceinline__ void sweep_chunk(const Chunk &ch, const uint32_t *__r
         if (active && lev == L) {
 #pragma unroll
             for (int k = 0; k < KMAX; ++k)
-                if (k >= ne && k < ne + ni) s -= vv[k] * ys[cc[k] - ch.row0];
+                if (k >= ne && k < ne + ni) s -= R.vv[k] * ys[R.cc[k] - ch.row0];
             for (int k = max(KMAX, ne); k < ne + ni; ++k) {
                 const int sl = base + k * nr;
                 s -= sval[sl] * ys[scol[sl] - ch.row0];
             }
-            ys[t] = s * dinv;
+            ys[t] = s * R.dinv;
         }
         // ys is this wavefront's own; its LDS operations execute in order,
         // so the next level's reads see this level's writes (the fences keep
@@ -671,6 +695,25 @@ __device__ __forceinline__ void sweep_chunk(const Chunk &ch, const uint32_t *__r
     }
     y_out = yv;
     m_out = m;
+}
+
+// One chunk of a task, both phases in a row.
+template <typename F, bool FWD, int KMAX, int MODE, typename TIn, typename TOut, class Wait = NoWait,
+          class Mem = PlainMem>
+__device__ __forceinline__ void sweep_chunk(const Chunk &ch, const uint32_t *__restrict__ meta,
+                                            const int *__restrict__ scol,
+                                            const F *__restrict__ sval,
+                                            const F *__restrict__ inv,
+                                            const TIn *__restrict__ in, TOut *__restrict__ out,
+                                            const CgArgs &cg, double alpha, F *ys, double &dacc,
+                                            const Wait &wait, const Mem &mem, F &y_out,
+                                            uint32_t &m_out, bool stream) {
+    // the first dependency a lane waits for, ahead of the chunk's loads
+    const int pre = wait.pre();
+    RowRegs<F, KMAX> R;
+    sweep_load<F, KMAX>(ch, meta, scol, sval, inv, stream, R);
+    sweep_finish<F, FWD, KMAX, MODE, TIn, TOut>(ch, R, scol, sval, in, out, cg, alpha, ys, dacc, wait, pre,
+                                                mem, y_out, m_out);
 }
 
 // FWD: y_i = (r_i - sum_{j<i} L_ij y_j) / L_ii over the rows of one color.
@@ -1127,6 +1170,7 @@ int launch_flow(iccg_ctx *c, DevSweep &d, const SweepArgs<F> &a, int pos0, int p
     const void *kfn = nullptr;
     switch (d.kmax) {
         case 4: kfn = reinterpret_cast<const void *>(&k_sweep_flow<F, FWD, 4, MODE, TIn, TOut>); break;
+        case 6:
         case 8: kfn = reinterpret_cast<const void *>(&k_sweep_flow<F, FWD, 8, MODE, TIn, TOut>); break;
         case 16: kfn = reinterpret_cast<const void *>(&k_sweep_flow<F, FWD, 16, MODE, TIn, TOut>); break;
         default: kfn = reinterpret_cast<const void *>(&k_sweep_flow<F, FWD, 32, MODE, TIn, TOut>); break;
@@ -1138,6 +1182,7 @@ int launch_flow(iccg_ctx *c, DevSweep &d, const SweepArgs<F> &a, int pos0, int p
 #define FLOW_ARGS a.tasks, a.chunks, a.meta, a.scol, a.sval, a.inv, fa, c->n, pin, pout, cg
     switch (d.kmax) {
         case 4: hipLaunchKernelGGL((k_sweep_flow<F, FWD, 4, MODE, TIn, TOut>), grid, block, 0, c->work, FLOW_ARGS); break;
+        case 6:
         case 8: hipLaunchKernelGGL((k_sweep_flow<F, FWD, 8, MODE, TIn, TOut>), grid, block, 0, c->work, FLOW_ARGS); break;
         case 16: hipLaunchKernelGGL((k_sweep_flow<F, FWD, 16, MODE, TIn, TOut>), grid, block, 0, c->work, FLOW_ARGS); break;
         default: hipLaunchKernelGGL((k_sweep_flow<F, FWD, 32, MODE, TIn, TOut>), grid, block, 0, c->work, FLOW_ARGS); break;
@@ -1194,6 +1239,7 @@ int launch_sweep_t(iccg_ctx *c, const void *in, void *out, const CgArgs &cg) {
             const dim3 grid((t1 - t0 + kSweepWaves - 1) / kSweepWaves), block(64 * kSweepWaves);
             switch (d.kmax) {
                 case 4: hipLaunchKernelGGL((k_sweep<F, FWD, 4, MODE, TIn, TOut>), grid, block, 0, c->work, SWEEP_ARGS); break;
+                case 6: hipLaunchKernelGGL((k_sweep<F, FWD, 6, MODE, TIn, TOut>), grid, block, 0, c->work, SWEEP_ARGS); break;
                 case 8: hipLaunchKernelGGL((k_sweep<F, FWD, 8, MODE, TIn, TOut>), grid, block, 0, c->work, SWEEP_ARGS); break;
                 case 16: hipLaunchKernelGGL((k_sweep<F, FWD, 16, MODE, TIn, TOut>), grid, block, 0, c->work, SWEEP_ARGS); break;
                 default: hipLaunchKernelGGL((k_sweep<F, FWD, 32, MODE, TIn, TOut>), grid, block, 0, c->work, SWEEP_ARGS); break;
@@ -1207,6 +1253,7 @@ int launch_sweep_t(iccg_ctx *c, const void *in, void *out, const CgArgs &cg) {
             const dim3 grid(nw), block(64 * wide_waves(d.max_width));
             switch (d.kmax) {
                 case 4: hipLaunchKernelGGL((k_sweep_wide<F, FWD, 4, MODE, TIn, TOut, wide_waves(4)>), grid, block, 0, c->work, WIDE_ARGS); break;
+                case 6:
                 case 8: hipLaunchKernelGGL((k_sweep_wide<F, FWD, 8, MODE, TIn, TOut, wide_waves(8)>), grid, block, 0, c->work, WIDE_ARGS); break;
                 case 16: hipLaunchKernelGGL((k_sweep_wide<F, FWD, 16, MODE, TIn, TOut, wide_waves(16)>), grid, block, 0, c->work, WIDE_ARGS); break;
                 default: hipLaunchKernelGGL((k_sweep_wide<F, FWD, 32, MODE, TIn, TOut, wide_waves(32)>), grid, block, 0, c->work, WIDE_ARGS); break;
@@ -1412,7 +1459,11 @@ int upload_sweep(iccg_ctx *c, const SweepPlan &plan, DevSweep &d) {
     d.nslots = static_cast<long long>(plan.slot_col.size());
     d.max_depth = plan.max_depth;
     d.max_width = plan.max_width;
-    d.kmax = plan.max_width <= 4 ? 4 : plan.max_width <= 8 ? 8 : plan.max_width <= 16 ? 16 : 32;
+    d.kmax = plan.max_width <= 4   ? 4
+             : plan.max_width <= 6 ? 6
+             : plan.max_width <= 8 ? 8
+             : plan.max_width <= 16 ? 16
+                                    : 32;
     d.color_task_ptr = plan.color_task_ptr;
     ICCG_CHECK(d.tasks.upload(plan.tasks.data(), plan.tasks.size(), c->work));
     d.ndeps = static_cast<long long>(plan.deps.size());
