@@ -242,6 +242,35 @@ int iccg_solve(iccg_ctx *c, const double *b, double *x, double tol, int maxit,
                int *iters, double *relres, double *relres_true);
 
 /*
+ * Blocks of right-hand sides: repeated solves that reuse one ordering and one
+ * factor (the paper amortizes the blocking cost over repeated solves,
+ * Sections 7.6 and 10).  k independent PCG solves, 1 <= k <= 16, whose
+ * kernels read A' and the factor once for all k columns (a workgroup of k
+ * wavefronts per sweep task and per SpMV slice, one wavefront per column).
+ * B, X: DEVICE FP64 [k][n], column-major (column j at offset j * n); X holds
+ * x0 on entry and the solutions on exit.  iters, relres, relres_true: host
+ * arrays of k (any may be NULL), per column as for iccg_solve.  Each column
+ * computes exactly what iccg_solve computes for it (same iterations, same x
+ * bit for bit) when the context has no wide tasks (wide_blocks = 0 or no
+ * block of more than 256 rows); with wide tasks the backward sweep's per-row
+ * sums group the terms by chunk instead of by piece (equal up to rounding).
+ * Returns ICCG_OK when every column converged, ICCG_ENAN if any column broke
+ * down, else ICCG_ENOCONV; ICCG_EINVAL for k outside [1, 16].  The context
+ * keeps work buffers of 7 k n doubles after the first call.
+ */
+int iccg_solve_multi(iccg_ctx *c, int k, const double *B, double *X, double tol, int maxit,
+                     int *iters, double *relres, double *relres_true);
+
+/* Z = (L L^T)^{-1} R column by column for k <= 16 columns (DEVICE FP64
+ * [k][n] column-major, no aliasing); each column equals ic_apply's output for
+ * it (under the wide-task condition of iccg_solve_multi). */
+int ic_apply_multi(iccg_ctx *c, int k, const double *R, double *Z);
+
+/* Q = A' P column by column for k <= 16 columns (DEVICE FP64 [k][n]
+ * column-major); each column equals iccg_spmv's output for it. */
+int iccg_spmv_multi(iccg_ctx *c, int k, const double *P, double *Q);
+
+/*
  * iccg_solve run eagerly with a HIP event pair around every SpMV and every
  * per-color sweep launch (the phase split of the paper's Table 8: forward
  * substitution, backward substitution, SpMV, other).  Same arguments and

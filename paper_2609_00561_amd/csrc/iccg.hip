@@ -121,10 +121,18 @@ __device__ __forceinline__ double thread_partial(const double *__restrict__ part
     return v;
 }
 
+// One workgroup per column of a block of right-hand sides (one for a single
+// vector): column c reduces part[c * part_ld ...] into its scalars sc[c].
 __global__ __launch_bounds__(kReduceThreads) void k_reduce(const double *__restrict__ part,
                                                            int np, DevScalars *sc, int op,
                                                            double *__restrict__ out,
-                                                           double *__restrict__ hist) {
+                                                           double *__restrict__ hist, int part_ld,
+                                                           int hist_ld) {
+    const int col = blockIdx.x;
+    part += static_cast<size_t>(col) * part_ld;
+    sc += col;
+    hist += static_cast<size_t>(col) * hist_ld;
+    if (out) out += col;
     if (op != OP_STORE && op != OP_TRUE && op != OP_BNORM && sc->done != DONE_RUNNING) return;
     double v = thread_partial<kReduceThreads>(part, np);
     v = block_sum<kReduceThreads>(v);
@@ -175,11 +183,18 @@ __global__ __launch_bounds__(kReduceThreads) void k_reduce(const double *__restr
 // backward sweep does not depend on the stopping test, so it can run first;
 // after the last iteration its z is simply unused.  Same sums, same order as
 // two k_reduce launches.
+// (one workgroup per column of a block of right-hand sides, as k_reduce)
 __global__ __launch_bounds__(kReduceThreads) void k_reduce_rr_beta(const double *__restrict__ rr_part,
                                                                    int n_rr,
                                                                    const double *__restrict__ rz_part,
                                                                    int n_rz, DevScalars *sc,
-                                                                   double *__restrict__ hist) {
+                                                                   double *__restrict__ hist, int part_ld,
+                                                                   int hist_ld) {
+    const int col = blockIdx.x;
+    rr_part += static_cast<size_t>(col) * part_ld;
+    rz_part += static_cast<size_t>(col) * part_ld;
+    sc += col;
+    hist += static_cast<size_t>(col) * hist_ld;
     if (sc->done != DONE_RUNNING) return;
     double a = thread_partial<kReduceThreads>(rr_part, n_rr);
     double b = thread_partial<kReduceThreads>(rz_part, n_rz);
@@ -200,8 +215,10 @@ __global__ __launch_bounds__(kReduceThreads) void k_reduce_rr_beta(const double 
     sc->rho = b;
 }
 
+// one workgroup per column
 __global__ void k_init_scalars(DevScalars *sc, double tol, int maxit, int hist_cap) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
+    sc += blockIdx.x;
+    if (threadIdx.x == 0) {
         sc->rho = sc->alpha = sc->beta = 0.0;
         sc->bnorm = 1.0;
         sc->relres = sc->relres_true = 0.0;
@@ -220,25 +237,24 @@ __global__ void k_init_scalars(DevScalars *sc, double tol, int maxit, int hist_c
 // ---------------------------------------------------------------------------
 enum SpmvMode : int { SP_PLAIN = 0, SP_RESID = 1 };
 constexpr int kSpmvSlicesPerWave = 2;
+// Columns (wavefronts) per workgroup of the block-of-right-hand-sides kernels.
+constexpr int kColWaves = 8;
 
-// One wavefront workgroup per slice (grid-stride over slices); WMAX slots of a
-// row are loaded into registers at once, then all gathers, then the row sum in
-// ascending column order.
-template <int MODE, int WMAX>
-__global__ __launch_bounds__(64) void k_spmv(int n, int nslices, const int4 *__restrict__ slices,
-                                             const int *__restrict__ col,
-                                             const double *__restrict__ val,
-                                             const double *__restrict__ x,
-                                             double *__restrict__ y,
-                                             const double *__restrict__ b,
-                                             double *__restrict__ part,
-                                             const DevScalars *sc) {
-    if (sc && sc->done != DONE_RUNNING) return;
+// One wavefront per kSpmvSlicesPerWave consecutive launch positions (grid-
+// stride over the slices); WMAX slots of a row are loaded into registers at
+// once, then all gathers, then the row sum in ascending column order.  wg:
+// the wavefront's logical index among G; lane 0 writes the wavefront's
+// partial sum to *part_out.  NT: stream the matrix with non-temporal loads.
+template <int MODE, int WMAX, bool NT>
+__device__ __forceinline__ void spmv_wave(int n, int nslices, const int4 *__restrict__ slices,
+                                          const int *__restrict__ col, const double *__restrict__ val,
+                                          const double *__restrict__ x, double *__restrict__ y,
+                                          const double *__restrict__ b, double *__restrict__ part_out,
+                                          int wg, int G) {
     constexpr int U = kSpmvSlicesPerWave;
-    const int lane = threadIdx.x;
-    const int wg = xcd_remap(blockIdx.x, gridDim.x);
+    const int lane = static_cast<int>(threadIdx.x) & 63;
     double acc = 0.0;
-    for (int lg0 = wg * U; lg0 < nslices; lg0 += gridDim.x * U) {
+    for (int lg0 = wg * U; lg0 < nslices; lg0 += G * U) {
         // U consecutive launch positions at once, so one wavefront has all of
         // their loads in flight together.  Launch-ordered slice record:
         // (slice, first slot, width).
@@ -253,14 +269,19 @@ __global__ __launch_bounds__(64) void k_spmv(int n, int nslices, const int4 *__r
             row[u] = lg0 + u < nslices ? rec.x * 64 + lane : n;
         }
         // the matrix streams through once (non-temporal: it should not push
-        // the gathered vector out of L2)
+        // the gathered vector out of L2), unless several wavefronts read it
 #pragma unroll
         for (int u = 0; u < U; ++u)
 #pragma unroll
             for (int k = 0; k < WMAX; ++k)
                 if (k < w[u]) {
-                    cc[u][k] = __builtin_nontemporal_load(col + off[u] + k * 64);
-                    vv[u][k] = __builtin_nontemporal_load(val + off[u] + k * 64);
+                    if (NT) {
+                        cc[u][k] = __builtin_nontemporal_load(col + off[u] + k * 64);
+                        vv[u][k] = __builtin_nontemporal_load(val + off[u] + k * 64);
+                    } else {
+                        cc[u][k] = col[off[u] + k * 64];
+                        vv[u][k] = val[off[u] + k * 64];
+                    }
                 }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -299,7 +320,48 @@ __global__ __launch_bounds__(64) void k_spmv(int n, int nslices, const int4 *__r
         }
     }
     const double t = wave_sum(acc);
-    if (threadIdx.x == 0) part[blockIdx.x] = t;
+    if ((threadIdx.x & 63) == 0) *part_out = t;
+}
+
+template <int MODE, int WMAX>
+__global__ __launch_bounds__(64) void k_spmv(int n, int nslices, const int4 *__restrict__ slices,
+                                             const int *__restrict__ col,
+                                             const double *__restrict__ val,
+                                             const double *__restrict__ x,
+                                             double *__restrict__ y,
+                                             const double *__restrict__ b,
+                                             double *__restrict__ part,
+                                             const DevScalars *sc) {
+    if (sc && sc->done != DONE_RUNNING) return;
+    spmv_wave<MODE, WMAX, true>(n, nslices, slices, col, val, x, y, b, part + blockIdx.x,
+                                xcd_remap(blockIdx.x, gridDim.x), gridDim.x);
+}
+
+// Block of right-hand sides (columns ld apart): workgroup g runs the slices
+// of k_spmv's workgroup g once per column, one wavefront per column (up to
+// kColWaves per workgroup, blockIdx.y counts groups of them); the
+// matrix comes from HBM once and from the compute unit's caches for the
+// other columns, and every column computes exactly what k_spmv computes for
+// it.  part[c * part_ld + g]; columns whose solve has stopped
+// skip their work.
+template <int MODE, int WMAX>
+__global__ __launch_bounds__(64 * kColWaves) void k_spmv_cols(int n, int nslices, const int4 *__restrict__ slices,
+                                                    const int *__restrict__ col,
+                                                    const double *__restrict__ val,
+                                                    const double *__restrict__ x,
+                                                    double *__restrict__ y,
+                                                    const double *__restrict__ b,
+                                                    double *__restrict__ part,
+                                                    const DevScalars *sc, int ld, int part_ld,
+                                                    int ncols) {
+    const int c = static_cast<int>(blockIdx.y) * kColWaves +
+                  __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) >> 6);
+    if (c >= ncols) return;
+    if (sc && sc[c].done != DONE_RUNNING) return;
+    const size_t off = static_cast<size_t>(c) * ld;
+    spmv_wave<MODE, WMAX, false>(n, nslices, slices, col, val, x + off, y + off, b ? b + off : nullptr,
+                                 part + static_cast<size_t>(c) * part_ld + blockIdx.x,
+                                 xcd_remap(blockIdx.x, gridDim.x), gridDim.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -374,6 +436,62 @@ __global__ __launch_bounds__(kVecThreads) void k_rescale_to_norm(int n, double *
     const double f = target / sqrt(*sumsq);
     for (int i = blockIdx.x * kVecThreads + threadIdx.x; i < n; i += gridDim.x * kVecThreads)
         v[i] = v[i] * f;
+}
+
+// Column versions of the vector kernels for a block of right-hand sides
+// (columns ld apart; blockIdx.y = column; same per-element arithmetic and,
+// for the dots, the same partial sums per column as the single-vector
+// kernels).  Columns whose solve has stopped skip their work.
+__global__ __launch_bounds__(kVecThreads) void k_dot_cols(int n, const double *__restrict__ a,
+                                                          const double *__restrict__ b,
+                                                          double *__restrict__ part, int ld,
+                                                          int part_ld) {
+    const size_t off = static_cast<size_t>(blockIdx.y) * ld;
+    a += off;
+    b += off;
+    double acc = 0.0;
+    const int wg = xcd_remap(blockIdx.x, gridDim.x);
+    for (int i = wg * kVecThreads + threadIdx.x; i < n; i += gridDim.x * kVecThreads)
+        acc += a[i] * b[i];
+    const double t = block_sum<kVecThreads>(acc);
+    if (threadIdx.x == 0) part[static_cast<size_t>(blockIdx.y) * part_ld + blockIdx.x] = t;
+}
+
+__global__ __launch_bounds__(64) void k_update_p_cols(int n, int nslices,
+                                                      const int *__restrict__ slice_order,
+                                                      double *__restrict__ x, double *__restrict__ p,
+                                                      const double *__restrict__ z,
+                                                      const DevScalars *sc, int ld) {
+    const DevScalars &s = sc[blockIdx.y];
+    if (s.done != DONE_RUNNING) return;
+    const double alpha = s.alpha, beta = s.beta;
+    const size_t off = static_cast<size_t>(blockIdx.y) * ld;
+    x += off;
+    p += off;
+    z += off;
+    const int wg = xcd_remap(blockIdx.x, gridDim.x);
+    for (int lg = wg; lg < nslices; lg += gridDim.x) {
+        const int i = slice_order[lg] * 64 + static_cast<int>(threadIdx.x);
+        if (i < n) {
+            const double pi = p[i];
+            x[i] = x[i] + alpha * pi;
+            p[i] = z[i] + beta * pi;
+        }
+    }
+}
+
+__global__ __launch_bounds__(kVecThreads) void k_axpy_alpha_cols(int n, double *__restrict__ x,
+                                                                 const double *__restrict__ p,
+                                                                 const DevScalars *sc, int ld) {
+    const DevScalars &s = sc[blockIdx.y];
+    if (s.done != DONE_CONVERGED && s.done != DONE_MAXIT) return;
+    const double alpha = s.alpha;
+    const size_t off = static_cast<size_t>(blockIdx.y) * ld;
+    x += off;
+    p += off;
+    const int wg = xcd_remap(blockIdx.x, gridDim.x);
+    for (int i = wg * kVecThreads + threadIdx.x; i < n; i += gridDim.x * kVecThreads)
+        x[i] = x[i] + alpha * p[i];
 }
 
 template <typename A, typename B>
@@ -716,6 +834,38 @@ __device__ __forceinline__ void sweep_chunk(const Chunk &ch, const uint32_t *__r
                                                 mem, y_out, m_out);
 }
 
+// One wavefront task: its chunks in the sweep's order (see k_sweep), and the
+// task's partial sum in *part_out.
+template <typename F, bool FWD, int KMAX, int MODE, typename TIn, typename TOut>
+__device__ __forceinline__ void sweep_task(const TaskRec &tr, const Chunk *__restrict__ chunks,
+                                           const uint32_t *__restrict__ meta,
+                                           const int *__restrict__ scol, const F *__restrict__ sval,
+                                           const F *__restrict__ inv, const TIn *__restrict__ in,
+                                           TOut *__restrict__ out, const CgArgs &cg, F *ys,
+                                           bool stream, double *part_out) {
+    const double alpha = (MODE == SW_CG_FWD) ? cg.sc->alpha : 0.0;
+    double dacc = 0.0;
+    F yv;
+    uint32_t m;
+    sweep_chunk<F, FWD, KMAX, MODE, TIn, TOut>(tr.first, meta, scol, sval, inv, in, out, cg, alpha,
+                                               ys, dacc, NoWait(), PlainMem(), yv, m, stream);
+    const int nchunks = tr.c1 - tr.c0;
+    for (int q = 1; q < nchunks; ++q) {
+        // later chunks of this task read earlier chunks' results from memory:
+        // this wavefront's stores complete before its next loads
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        const Chunk ch = chunks[FWD ? tr.c0 + q : tr.c1 - 1 - q];
+        sweep_chunk<F, FWD, KMAX, MODE, TIn, TOut>(ch, meta, scol, sval, inv, in, out, cg, alpha,
+                                                   ys, dacc, NoWait(), PlainMem(), yv, m, stream);
+    }
+    if (MODE != SW_APPLY) {
+        const double tsum = wave_sum(dacc);
+        if ((threadIdx.x & 63) == 0) *part_out = tsum;
+    }
+}
+
 // FWD: y_i = (r_i - sum_{j<i} L_ij y_j) / L_ii over the rows of one color.
 // !FWD: z_i = (y_i - sum_{j>i} L_ji z_j) / L_ii.
 // One wavefront per task, one lane per row of the current chunk.  All of the
@@ -743,32 +893,50 @@ __global__ __launch_bounds__(64 * kSweepWaves) void k_sweep(const TaskRec *__res
     const int nwg = (ntasks_color + kSweepWaves - 1) / kSweepWaves;
     const int local = xcd_remap(blockIdx.x, nwg) * kSweepWaves + wave;
     if (local >= ntasks_color) return;
-    F *ys = ys_all[wave];
     const int task = task_base + local;
-    const double alpha = (MODE == SW_CG_FWD) ? cg.sc->alpha : 0.0;
-    double dacc = 0.0;
-    F yv;
-    uint32_t m;
     const TaskRec tr = tasks[task];
     if (tr.wide >= 0) return;   // run by k_sweep_wide
-    const bool stream = ntasks_color >= kStreamTasks;
-    sweep_chunk<F, FWD, KMAX, MODE, TIn, TOut>(tr.first, meta, scol, sval, inv, in, out, cg, alpha,
-                                               ys, dacc, NoWait(), PlainMem(), yv, m, stream);
-    const int nchunks = tr.c1 - tr.c0;
-    for (int q = 1; q < nchunks; ++q) {
-        // later chunks of this task read earlier chunks' results from memory:
-        // this wavefront's stores complete before its next loads
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-        __builtin_amdgcn_wave_barrier();
-        const Chunk ch = chunks[FWD ? tr.c0 + q : tr.c1 - 1 - q];
-        sweep_chunk<F, FWD, KMAX, MODE, TIn, TOut>(ch, meta, scol, sval, inv, in, out, cg, alpha,
-                                                   ys, dacc, NoWait(), PlainMem(), yv, m, stream);
-    }
-    if (MODE != SW_APPLY) {
-        const double tsum = wave_sum(dacc);
-        if ((threadIdx.x & 63) == 0) cg.part[task] = tsum;
-    }
+    sweep_task<F, FWD, KMAX, MODE, TIn, TOut>(tr, chunks, meta, scol, sval, inv, in, out, cg, ys_all[wave],
+                                              ntasks_color >= kStreamTasks, cg.part ? cg.part + task : nullptr);
+}
+
+// Block of right-hand sides (columns ld apart): workgroup g runs task g of
+// the color once per column, one wavefront per column (up to kColWaves
+// columns per workgroup, blockIdx.y counts groups of them), so the schedule
+// comes from HBM once and from the compute unit's caches for the other
+// columns; every column computes exactly what k_sweep computes for it.
+// Blocks of more than 64 rows run as chunk sequences (no wide tasks).
+// Partial sums at part[c * part_ld + task]; columns whose solve has stopped
+// skip their work.
+template <typename F, bool FWD, int KMAX, int MODE, typename TIn, typename TOut>
+__global__ __launch_bounds__(64 * kColWaves) void k_sweep_cols(const TaskRec *__restrict__ tasks,
+                                                     const Chunk *__restrict__ chunks,
+                                                     const uint32_t *__restrict__ meta,
+                                                     const int *__restrict__ scol,
+                                                     const F *__restrict__ sval,
+                                                     const F *__restrict__ inv, int task_base,
+                                                     int ntasks_color, const TIn *__restrict__ in,
+                                                     TOut *__restrict__ out, CgArgs cg, int ld,
+                                                     int part_ld, int ncols) {
+    const int w = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) >> 6);
+    const int c = static_cast<int>(blockIdx.y) * kColWaves + w;
+    if (c >= ncols) return;
+    if (cg.sc && cg.sc[c].done != DONE_RUNNING) return;
+    __shared__ F ys_all[kColWaves][kChunkRows];
+    const int local = xcd_remap(blockIdx.x, gridDim.x);
+    if (local >= ntasks_color) return;
+    const int task = task_base + local;
+    const TaskRec tr = tasks[task];
+    const size_t off = static_cast<size_t>(c) * ld;
+    CgArgs cc = cg;
+    if (cc.r) cc.r += off;
+    if (cc.q) cc.q += off;
+    if (cc.rdot) cc.rdot += off;
+    if (cc.sc) cc.sc += c;
+    sweep_task<F, FWD, KMAX, MODE, TIn, TOut>(tr, chunks, meta, scol, sval, inv, in ? in + off : nullptr,
+                                              out + off, cc, ys_all[w], false,
+                                              cg.part ? cg.part + static_cast<size_t>(c) * part_ld + task
+                                                      : nullptr);
 }
 
 // Wide task (see WidePlan): one block of more than 64 rows, run piece by
@@ -1345,7 +1513,7 @@ void *ytmp(iccg_ctx *c) { return c->fp32() ? static_cast<void *>(c->y32.p) : c->
 
 int launch_reduce(iccg_ctx *c, int np, int op, double *out) {
     hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kReduceThreads), 0, c->work, c->part.p, np,
-                       c->scal.p, op, out, c->hist.p);
+                       c->scal.p, op, out, c->hist.p, 0, 0);
     HIP_CHECK(hipGetLastError());
     return ICCG_OK;
 }
@@ -1378,7 +1546,7 @@ int enqueue_iteration(iccg_ctx *c, long long j) {
     g.sc = sc;
     ICCG_CHECK((launch_sweep<false, SW_DOT_BWD>(c, ytmp(c), c->z.p, g)));
     hipLaunchKernelGGL(k_reduce_rr_beta, dim3(1), dim3(kReduceThreads), 0, c->work, c->part_rr.p,
-                       c->fwd.ntasks, c->part.p, c->bwd.ntasks, sc, c->hist.p);
+                       c->fwd.ntasks, c->part.p, c->bwd.ntasks, sc, c->hist.p, 0, 0);
     HIP_CHECK(hipGetLastError());
     return ICCG_OK;
 }
@@ -1748,6 +1916,241 @@ int solve_impl(iccg_ctx *c, const double *b, double *x, double tol, int maxit, i
     return set_error(ICCG_ENOCONV, "maxit reached at relres " + std::to_string(h.relres));
 }
 
+// ---------------------------------------------------------------------------
+// blocks of right-hand sides: k columns of n (column-major, ld = n), one
+// independent CG per column sharing every read of the matrix and the factor
+// ---------------------------------------------------------------------------
+constexpr int kMaxCols = 16;
+
+// One color of a sweep for every column: workgroups of k wavefronts.
+template <typename F, bool FWD, int MODE>
+int launch_sweep_cols_t(iccg_ctx *c, int k, const void *in, void *out, const CgArgs &cg, int part_ld) {
+    using TIn = typename std::conditional<FWD, double, F>::type;
+    using TOut = typename std::conditional<FWD, F, double>::type;
+    DevSweep &d = FWD ? c->fwd : c->bwd;
+    const SweepArgs<F> a = sweep_args<F>(c, d);
+    const TIn *pin = static_cast<const TIn *>(in);
+    TOut *pout = static_cast<TOut *>(out);
+    const int ld = c->n;
+    for (int step = 0; step < c->ncolors; ++step) {
+        const int col = FWD ? step : c->ncolors - 1 - step;
+        const int t0 = d.color_task_ptr[col], t1 = d.color_task_ptr[col + 1];
+        if (t1 == t0) continue;
+        const dim3 grid(t1 - t0, (k + kColWaves - 1) / kColWaves), block(64 * std::min(k, kColWaves));
+#define COLS_ARGS a.tasks, a.chunks, a.meta, a.scol, a.sval, a.inv, t0, t1 - t0, pin, pout, cg, ld, part_ld, k
+        switch (d.kmax) {
+            case 4: hipLaunchKernelGGL((k_sweep_cols<F, FWD, 4, MODE, TIn, TOut>), grid, block, 0, c->work, COLS_ARGS); break;
+            case 6: hipLaunchKernelGGL((k_sweep_cols<F, FWD, 6, MODE, TIn, TOut>), grid, block, 0, c->work, COLS_ARGS); break;
+            case 8: hipLaunchKernelGGL((k_sweep_cols<F, FWD, 8, MODE, TIn, TOut>), grid, block, 0, c->work, COLS_ARGS); break;
+            case 16: hipLaunchKernelGGL((k_sweep_cols<F, FWD, 16, MODE, TIn, TOut>), grid, block, 0, c->work, COLS_ARGS); break;
+            default: hipLaunchKernelGGL((k_sweep_cols<F, FWD, 32, MODE, TIn, TOut>), grid, block, 0, c->work, COLS_ARGS); break;
+        }
+#undef COLS_ARGS
+        HIP_CHECK(hipGetLastError());
+    }
+    return ICCG_OK;
+}
+
+template <bool FWD, int MODE>
+int launch_sweep_cols(iccg_ctx *c, int k, const void *in, void *out, const CgArgs &cg, int part_ld) {
+    return c->fp32() ? launch_sweep_cols_t<float, FWD, MODE>(c, k, in, out, cg, part_ld)
+                     : launch_sweep_cols_t<double, FWD, MODE>(c, k, in, out, cg, part_ld);
+}
+
+int launch_spmv_cols(iccg_ctx *c, int k, int mode, const double *x, double *y, const double *b,
+                     const DevScalars *sc, double *part, int part_ld) {
+    const dim3 grid(c->spmv_blocks, (k + kColWaves - 1) / kColWaves), block(64 * std::min(k, kColWaves));
+    const int ld = c->n;
+#define SPMVC_ARGS c->n, c->nslices, c->sell_rec.p, c->sell_col.p, c->sell_val.p, x, y, b, part, sc, ld, part_ld, k
+#define SPMVC_W(M)                                                                                    \
+    switch (c->sell_wmax) {                                                                           \
+        case 8: hipLaunchKernelGGL((k_spmv_cols<M, 8>), grid, block, 0, c->work, SPMVC_ARGS); break;   \
+        case 16: hipLaunchKernelGGL((k_spmv_cols<M, 16>), grid, block, 0, c->work, SPMVC_ARGS); break; \
+        default: hipLaunchKernelGGL((k_spmv_cols<M, 32>), grid, block, 0, c->work, SPMVC_ARGS); break; \
+    }
+    if (mode == SP_PLAIN) {
+        SPMVC_W(SP_PLAIN)
+    } else {
+        SPMVC_W(SP_RESID)
+    }
+#undef SPMVC_W
+#undef SPMVC_ARGS
+    HIP_CHECK(hipGetLastError());
+    return ICCG_OK;
+}
+
+int multi_part_ld(const iccg_ctx *c) { return static_cast<int>(c->part.count); }
+void *mytmp(iccg_ctx *c) { return c->fp32() ? static_cast<void *>(c->my32.p) : c->my64.p; }
+
+// Work buffers for k columns (kept for later calls with at most as many).
+int ensure_multi(iccg_ctx *c, int k) {
+    if (!c->h_mscal)
+        HIP_CHECK(hipHostMalloc(reinterpret_cast<void **>(&c->h_mscal), sizeof(DevScalars) * kMaxCols,
+                                hipHostMallocDefault));
+    if (k <= c->mk) return ICCG_OK;
+    const size_t nk = static_cast<size_t>(c->n) * k;
+    for (DevArray<double> *v : {&c->mx, &c->mr, &c->mz, &c->mp, &c->mq, &c->mb}) ICCG_CHECK(v->alloc(nk));
+    if (c->fp32()) ICCG_CHECK(c->my32.alloc(nk));
+    else ICCG_CHECK(c->my64.alloc(nk));
+    const size_t np = static_cast<size_t>(multi_part_ld(c));
+    ICCG_CHECK(c->mpart.alloc(np * k));
+    ICCG_CHECK(c->mpart_rr.alloc(np * k));
+    ICCG_CHECK(c->mscal.alloc(k));
+    c->mk = k;
+    return ICCG_OK;
+}
+
+int launch_reduce_cols(iccg_ctx *c, int k, const double *part, int np, int op, double *out) {
+    hipLaunchKernelGGL(k_reduce, dim3(k), dim3(kReduceThreads), 0, c->work, part, np, c->mscal.p, op, out,
+                       c->mhist.p, multi_part_ld(c), c->mhist_cap);
+    HIP_CHECK(hipGetLastError());
+    return ICCG_OK;
+}
+
+// One CG iteration of every column (the single-vector iteration's kernels,
+// column by column; stopped columns skip their work).
+int enqueue_iteration_multi(iccg_ctx *c, int k) {
+    const int pld = multi_part_ld(c);
+    DevScalars *sc = c->mscal.p;
+    hipLaunchKernelGGL(k_update_p_cols, dim3(c->nslices, k), dim3(64), 0, c->work, c->n, c->nslices,
+                       c->sell_order.p, c->mx.p, c->mp.p, c->mz.p, sc, c->n);
+    HIP_CHECK(hipGetLastError());
+    ICCG_CHECK(launch_spmv_cols(c, k, SP_PLAIN, c->mp.p, c->mq.p, nullptr, sc, c->mpart.p, pld));
+    ICCG_CHECK(launch_reduce_cols(c, k, c->mpart.p, c->spmv_blocks, OP_ALPHA, nullptr));
+    CgArgs f = no_cg();
+    f.r = c->mr.p;
+    f.q = c->mq.p;
+    f.part = c->mpart_rr.p;
+    f.sc = sc;
+    ICCG_CHECK((launch_sweep_cols<true, SW_CG_FWD>(c, k, nullptr, mytmp(c), f, pld)));
+    CgArgs g = no_cg();
+    g.rdot = c->mr.p;
+    g.part = c->mpart.p;
+    g.sc = sc;
+    ICCG_CHECK((launch_sweep_cols<false, SW_DOT_BWD>(c, k, mytmp(c), c->mz.p, g, pld)));
+    hipLaunchKernelGGL(k_reduce_rr_beta, dim3(k), dim3(kReduceThreads), 0, c->work, c->mpart_rr.p,
+                       c->fwd.ntasks, c->mpart.p, c->bwd.ntasks, sc, c->mhist.p, pld, c->mhist_cap);
+    HIP_CHECK(hipGetLastError());
+    return ICCG_OK;
+}
+
+int run_batch_multi(iccg_ctx *c, int k, int iters) {
+    if (!c->opt.use_graph) {
+        for (int j = 0; j < iters; ++j) ICCG_CHECK(enqueue_iteration_multi(c, k));
+        return ICCG_OK;
+    }
+    if (!c->mgraph || c->mgraph_iters != iters || c->mgraph_k != k) {
+        if (c->mgraph) {
+            HIP_CHECK(hipGraphExecDestroy(c->mgraph));
+            c->mgraph = nullptr;
+        }
+        HIP_CHECK(hipStreamBeginCapture(c->work, hipStreamCaptureModeThreadLocal));
+        int st = ICCG_OK;
+        for (int j = 0; j < iters && st == ICCG_OK; ++j) st = enqueue_iteration_multi(c, k);
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(c->work, &g);
+        if (st != ICCG_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return st;
+        }
+        if (e != hipSuccess) return set_error(ICCG_EHIP, std::string("graph capture: ") + hipGetErrorString(e));
+        e = hipGraphInstantiate(&c->mgraph, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) {
+            c->mgraph = nullptr;
+            return set_error(ICCG_EHIP, std::string("graph instantiate: ") + hipGetErrorString(e));
+        }
+        c->mgraph_iters = iters;
+        c->mgraph_k = k;
+    }
+    HIP_CHECK(hipGraphLaunch(c->mgraph, c->work));
+    return ICCG_OK;
+}
+
+int read_mscalars(iccg_ctx *c, int k) {
+    HIP_CHECK(hipMemcpyAsync(c->h_mscal, c->mscal.p, sizeof(DevScalars) * k, hipMemcpyDeviceToHost, c->work));
+    HIP_CHECK(hipStreamSynchronize(c->work));
+    return ICCG_OK;
+}
+
+int solve_multi_impl(iccg_ctx *c, int k, const double *B, double *X, double tol, int maxit, int *iters,
+                     double *relres, double *relres_true) {
+    if (k < 1 || k > kMaxCols) return set_error(ICCG_EINVAL, "need 1 <= k <= 16 right-hand sides");
+    if (!B || !X) return set_error(ICCG_EINVAL, "null B or X");
+    if (!(tol >= 0.0) || maxit < 0) return set_error(ICCG_EINVAL, "need tol >= 0 and maxit >= 0");
+    if (!c->has_factor) return set_error(ICCG_ESTATE, "no factor: call ic0_factor or iccg_set_factor first");
+    ICCG_CHECK(ensure_multi(c, k));
+    const int hist_cap = maxit + 1;
+    if (c->mhist.count < static_cast<size_t>(hist_cap) * k || c->mhist_cap != hist_cap) {
+        if (c->mhist.count < static_cast<size_t>(hist_cap) * k)
+            ICCG_CHECK(c->mhist.alloc(static_cast<size_t>(hist_cap) * k));
+        c->mhist_cap = hist_cap;
+        if (c->mgraph) {
+            HIP_CHECK(hipGraphExecDestroy(c->mgraph));
+            c->mgraph = nullptr;
+        }
+    }
+    const int n = c->n;
+    const size_t nk = static_cast<size_t>(n) * k;
+    const int pld = multi_part_ld(c);
+    hipStream_t s = c->work;
+    HIP_CHECK(hipEventRecord(c->ev_t0, s));
+    HIP_CHECK(hipMemcpyAsync(c->mb.p, B, sizeof(double) * nk, hipMemcpyDeviceToDevice, s));
+    HIP_CHECK(hipMemcpyAsync(c->mx.p, X, sizeof(double) * nk, hipMemcpyDeviceToDevice, s));
+    hipLaunchKernelGGL(k_init_scalars, dim3(k), dim3(64), 0, s, c->mscal.p, tol, maxit, hist_cap);
+    hipLaunchKernelGGL(k_dot_cols, dim3(c->vec_blocks, k), dim3(kVecThreads), 0, s, n, c->mb.p, c->mb.p,
+                       c->mpart.p, n, pld);
+    HIP_CHECK(hipGetLastError());
+    ICCG_CHECK(launch_reduce_cols(c, k, c->mpart.p, c->vec_blocks, OP_BNORM, nullptr));
+    // r = b - A x, stopping test on the initial residual
+    ICCG_CHECK(launch_spmv_cols(c, k, SP_RESID, c->mx.p, c->mr.p, c->mb.p, nullptr, c->mpart.p, pld));
+    ICCG_CHECK(launch_reduce_cols(c, k, c->mpart.p, c->spmv_blocks, OP_INIT_RR, nullptr));
+    // z = M^{-1} r, rho = (r, z); p = 0 and beta = 0 make the first update p = z
+    CgArgs init = no_cg();
+    init.sc = c->mscal.p;
+    ICCG_CHECK((launch_sweep_cols<true, SW_APPLY>(c, k, c->mr.p, mytmp(c), init, pld)));
+    init.rdot = c->mr.p;
+    init.part = c->mpart.p;
+    ICCG_CHECK((launch_sweep_cols<false, SW_DOT_BWD>(c, k, mytmp(c), c->mz.p, init, pld)));
+    ICCG_CHECK(launch_reduce_cols(c, k, c->mpart.p, c->bwd.ntasks, OP_RHO, nullptr));
+    hipLaunchKernelGGL(k_fill, dim3(c->vec_blocks), dim3(kVecThreads), 0, s, static_cast<int>(nk), c->mp.p, 0.0);
+    HIP_CHECK(hipGetLastError());
+    ICCG_CHECK(read_mscalars(c, k));
+    auto running = [&]() {
+        for (int j = 0; j < k; ++j)
+            if (c->h_mscal[j].done == DONE_RUNNING) return true;
+        return false;
+    };
+    const int batch = std::max(1, c->opt.check_every);
+    while (running()) {
+        ICCG_CHECK(run_batch_multi(c, k, batch));
+        ICCG_CHECK(read_mscalars(c, k));
+    }
+    hipLaunchKernelGGL(k_axpy_alpha_cols, dim3(c->vec_blocks, k), dim3(kVecThreads), 0, s, n, c->mx.p, c->mp.p,
+                       c->mscal.p, n);
+    HIP_CHECK(hipGetLastError());
+    ICCG_CHECK(launch_spmv_cols(c, k, SP_RESID, c->mx.p, c->mq.p, c->mb.p, nullptr, c->mpart.p, pld));
+    ICCG_CHECK(launch_reduce_cols(c, k, c->mpart.p, c->spmv_blocks, OP_TRUE, nullptr));
+    HIP_CHECK(hipMemcpyAsync(X, c->mx.p, sizeof(double) * nk, hipMemcpyDeviceToDevice, s));
+    HIP_CHECK(hipEventRecord(c->ev_t1, s));
+    ICCG_CHECK(read_mscalars(c, k));
+    float ms = 0.0f;
+    HIP_CHECK(hipEventElapsedTime(&ms, c->ev_t0, c->ev_t1));
+    c->last_ms = ms;
+    int status = ICCG_OK;
+    for (int j = 0; j < k; ++j) {
+        const DevScalars &h = c->h_mscal[j];
+        if (iters) iters[j] = h.iter;
+        if (relres) relres[j] = h.relres;
+        if (relres_true) relres_true[j] = h.relres_true;
+        if (h.done == DONE_NAN) status = ICCG_ENAN;
+        else if (h.done != DONE_CONVERGED && status == ICCG_OK) status = ICCG_ENOCONV;
+    }
+    if (status == ICCG_ENAN) return set_error(ICCG_ENAN, "CG breakdown in a column: (p, Ap) <= 0 or a non-finite scalar");
+    if (status == ICCG_ENOCONV) return set_error(ICCG_ENOCONV, "maxit reached in a column");
+    return ICCG_OK;
+}
+
 template <typename F>
 int entry(iccg_ctx *c, F &&body) {
     try {
@@ -1988,7 +2391,7 @@ int iccg_spmv_dot_noalloc(iccg_ctx *c, const double *p, double *q, double *pq_de
         if (!part) return set_error(ICCG_ESTATE, "static scratch not resolved for this device");
         ICCG_CHECK(launch_spmv(c, SP_PLAIN, p, q, nullptr, nullptr, part));
         hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kReduceThreads), 0, c->work, part, c->spmv_blocks,
-                           c->scal.p, OP_STORE, pq_dev, c->hist.p);
+                           c->scal.p, OP_STORE, pq_dev, c->hist.p, 0, 0);
         HIP_CHECK(hipGetLastError());
         return ICCG_OK;
     });
@@ -2032,6 +2435,35 @@ int iccg_mpnn_smooth_probes(iccg_ctx *c, const double *z, int nprobes, double *o
 int iccg_solve(iccg_ctx *c, const double *b, double *x, double tol, int maxit, int *iters,
                double *relres, double *relres_true) {
     return entry(c, [&]() -> int { return solve_impl(c, b, x, tol, maxit, iters, relres, relres_true); });
+}
+
+int iccg_solve_multi(iccg_ctx *c, int k, const double *B, double *X, double tol, int maxit, int *iters,
+                     double *relres, double *relres_true) {
+    return entry(c, [&]() -> int {
+        return solve_multi_impl(c, k, B, X, tol, maxit, iters, relres, relres_true);
+    });
+}
+
+int ic_apply_multi(iccg_ctx *c, int k, const double *R, double *Z) {
+    return entry(c, [&]() -> int {
+        if (k < 1 || k > kMaxCols) return set_error(ICCG_EINVAL, "need 1 <= k <= 16 columns");
+        if (!R || !Z) return set_error(ICCG_EINVAL, "null block vector");
+        if (R == Z) return set_error(ICCG_EINVAL, "R and Z must not alias");
+        if (!c->has_factor) return set_error(ICCG_ESTATE, "no factor");
+        ICCG_CHECK(ensure_multi(c, k));
+        ICCG_CHECK((launch_sweep_cols<true, SW_APPLY>(c, k, R, mytmp(c), no_cg(), multi_part_ld(c))));
+        ICCG_CHECK((launch_sweep_cols<false, SW_APPLY>(c, k, mytmp(c), Z, no_cg(), multi_part_ld(c))));
+        return ICCG_OK;
+    });
+}
+
+int iccg_spmv_multi(iccg_ctx *c, int k, const double *P, double *Q) {
+    return entry(c, [&]() -> int {
+        if (k < 1 || k > kMaxCols) return set_error(ICCG_EINVAL, "need 1 <= k <= 16 columns");
+        if (!P || !Q || P == Q) return set_error(ICCG_EINVAL, "need distinct P and Q");
+        ICCG_CHECK(ensure_multi(c, k));
+        return launch_spmv_cols(c, k, SP_PLAIN, P, Q, nullptr, nullptr, c->mpart.p, multi_part_ld(c));
+    });
 }
 
 int iccg_profile_solve(iccg_ctx *c, const double *b, double *x, double tol, int maxit,

@@ -193,6 +193,16 @@ struct iccg_ctx {
     DevArray<int> dint;
     DevArray<int> sweep_err;       // set by a sweep wait that exceeded its spin limit
     DevScalars *h_scal = nullptr;   // pinned
+    // blocks of right-hand sides (iccg_solve_multi): k columns of n, ld = n
+    int mk = 0;                     // columns the buffers below hold
+    DevArray<double> mx, mr, mz, mp, mq, mb, my64;
+    DevArray<float> my32;
+    DevArray<double> mpart, mpart_rr, mhist;
+    DevArray<DevScalars> mscal;
+    DevScalars *h_mscal = nullptr;  // pinned, kMaxCols of them
+    int mhist_cap = 0;
+    hipGraphExec_t mgraph = nullptr;
+    int mgraph_iters = 0, mgraph_k = 0;
     int h_err = 0;
     int nslices = 0;                // sliced ELL copy of A' for the SpMV
     int sell_wmax = 8;              // register slots per row in k_spmv
@@ -215,7 +225,9 @@ struct iccg_ctx {
     ~iccg_ctx() {
         if (feat) destroy_learned_features(feat);
         if (graph) (void)hipGraphExecDestroy(graph);
+        if (mgraph) (void)hipGraphExecDestroy(mgraph);
         if (h_scal) (void)hipHostFree(h_scal);
+        if (h_mscal) (void)hipHostFree(h_mscal);
         if (ev_in) (void)hipEventDestroy(ev_in);
         if (ev_out) (void)hipEventDestroy(ev_out);
         if (ev_t0) (void)hipEventDestroy(ev_t0);

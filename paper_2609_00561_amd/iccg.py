@@ -45,6 +45,7 @@ EXPORTS = [
     "iccg_destroy", "iccg_mpnn_param_count", "iccg_mpnn_create", "iccg_mpnn_get_params",
     "iccg_mpnn_set_params", "iccg_mpnn_loss_grad", "iccg_mpnn_train_step", "iccg_mpnn_predict",
     "iccg_mpnn_destroy", "iccg_mpnn_smooth_probes", "iccg_spmv_dot_noalloc",
+    "iccg_solve_multi", "ic_apply_multi", "iccg_spmv_multi",
 ]
 
 
@@ -118,6 +119,9 @@ def load():
         "iccg_spmv_dot_noalloc": (i, [vp, vp, vp, vp]),
         "iccg_dot": (i, [vp, vp, vp, dp]),
         "iccg_solve": (i, [vp, vp, vp, d, i, ip, dp, dp]),
+        "iccg_solve_multi": (i, [vp, i, vp, vp, d, i, vp, vp, vp]),
+        "ic_apply_multi": (i, [vp, i, vp, vp]),
+        "iccg_spmv_multi": (i, [vp, i, vp, vp]),
         "iccg_residual_history": (i, [vp, vp, i]),
         "iccg_profile_solve": (i, [vp, vp, vp, d, i, vp]),
         "iccg_get_info": (i, [vp, ctypes.POINTER(_Info)]),
@@ -356,6 +360,32 @@ class Context:
         if st != ICCG_OK and (raise_on_noconv or st != ICCG_ENOCONV):
             _check(st, "iccg_solve")
         return {"status": st, "iters": it.value, "relres": rr.value, "relres_true": rt.value}
+
+    def solve_multi(self, B, X, tol: float = 1e-8, maxit: int = 10000, raise_on_noconv: bool = True):
+        """k independent solves: B, X device tensors [k, n] (row j = column j of
+        the block); X holds x0 and receives the solutions."""
+        k = self._block_k(B, X)
+        iters = np.zeros(k, dtype=np.int32)
+        rr = np.zeros(k)
+        rt = np.zeros(k)
+        st = load().iccg_solve_multi(self._h, k, _ptr(B), _ptr(X), float(tol), int(maxit),
+                                     iters.ctypes.data, rr.ctypes.data, rt.ctypes.data)
+        if st != ICCG_OK and not (st == ICCG_ENOCONV and not raise_on_noconv):
+            _check(st, "iccg_solve_multi")
+        return {"status": st, "iters": iters, "relres": rr, "relres_true": rt}
+
+    def ic_apply_multi(self, R, Z):
+        k = self._block_k(R, Z)
+        _check(load().ic_apply_multi(self._h, k, _ptr(R), _ptr(Z)), "ic_apply_multi")
+
+    def spmv_multi(self, P, Q):
+        k = self._block_k(P, Q)
+        _check(load().iccg_spmv_multi(self._h, k, _ptr(P), _ptr(Q)), "iccg_spmv_multi")
+
+    def _block_k(self, A, B) -> int:
+        if A.dim() != 2 or A.shape != B.shape or A.shape[1] != self.n:
+            raise ValueError("block vectors must both be [k, n]")
+        return int(A.shape[0])
 
     def profile_solve(self, b, x, tol: float = 1e-8, maxit: int = 10000) -> dict:
         out = np.zeros(10, dtype=np.float64)
