@@ -96,9 +96,12 @@ typedef struct {
                            The forward sweep is bit-identical either way; the
                            backward sweep's per-row sums group the entries by
                            piece instead of by chunk (equal up to rounding).   */
+    int   host_factor;  /* ic0_factor on the device over the forward sweep's
+                           schedule (0, default) or serially on the host (1);
+                           both give the serial FP64 factorization bit for bit */
 } iccg_options;
 
-/* Fills *opt with the defaults above (FP64, null stream, 32, 64, 1, 0, 0, 0, 1). */
+/* Fills *opt with the defaults above (FP64, null stream, 32, 64, 1, 0, 0, 0, 1, 0). */
 void iccg_default_options(iccg_options *opt);
 
 /* ------------------------------------------------------------------------ */
@@ -171,10 +174,15 @@ int iccg_setup(iccg_ctx **out, int n, const int *rowptr, const int *col, const d
 
 /*
  * IC(0) factor of A' (Section 3): L with pattern(L) = lower(A') and
- * (L L^T)_ij = a'_ij on that pattern, computed in FP64 on the host and
- * uploaded (rounded to FP32 for ICCG_FP32).  On a pivot that is not > 0 or
- * not finite returns ICCG_EBREAKDOWN with *breakdown_row set (else -1); the
- * context then holds no factor.
+ * (L L^T)_ij = a'_ij on that pattern, in FP64 (rounded to FP32 for the sweeps
+ * of ICCG_FP32).  By default on the device: one launch per color over the
+ * forward sweep's schedule (blocks of a color in parallel, the rows of a
+ * chunk level by level), each row computed in the serial order of operations
+ * without fused multiply-adds, so the result equals the serial
+ * factorization bit for bit; iccg_options.host_factor = 1 computes it
+ * serially on the host instead.  On a pivot that is not > 0 or not finite
+ * returns ICCG_EBREAKDOWN with *breakdown_row set to the first such row
+ * (else -1); the context then holds no factor.
  */
 int ic0_factor(iccg_ctx *c, int *breakdown_row);
 

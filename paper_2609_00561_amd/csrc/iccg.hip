@@ -549,6 +549,76 @@ __global__ void k_check_factor(int n, const int *__restrict__ rowptr, const int 
     }
 }
 
+// IC(0) of A' on the device (Section 3; the LL^T form with L_ii = sqrt of the
+// pivot), over the forward sweep's schedule: one launch per color, one
+// wavefront per task, its chunks in order, and inside a chunk the rows of one
+// level at a time (a row's lower neighbours lie in earlier colors, earlier
+// chunks of its task or lower levels of its chunk, exactly the forward
+// substitution's dependencies).  One lane computes one row, in the serial
+// order of operations: for each lower entry k ascending,
+//   L_ik = (a_ik - sum_{j<k, j in pat(i) and pat(k)} L_ij L_kj) / L_kk
+// with the sum taken by a merge in ascending j, then the pivot
+// d = a_ii - sum_k L_ik^2 ascending and L_ii = sqrt(d).  Multiplications and
+// subtractions are not fused, so every entry equals the serial FP64
+// factorization's bit for bit.  A pivot that is not > 0 or not finite lowers
+// *bad to its row (the first failing row in serial order is the smallest:
+// rows before it do not depend on it).
+__device__ void ic0_row(int i, const int *__restrict__ rowptr, const int *__restrict__ col,
+                        const double *__restrict__ val, const int *__restrict__ dpos,
+                        double *__restrict__ L, int *bad) {
+#pragma clang fp contract(off)
+    const int r0 = rowptr[i], di = dpos[i];
+    for (int p = r0; p < di; ++p) {
+        const int k = col[p];
+        double s = val[p];
+        int a = r0, b = rowptr[k];
+        const int be = dpos[k];
+        while (a < p && b < be) {
+            const int ca = col[a], cb = col[b];
+            if (ca < cb) {
+                ++a;
+            } else if (ca > cb) {
+                ++b;
+            } else {
+                s -= L[a] * L[b];
+                ++a;
+                ++b;
+            }
+        }
+        L[p] = s / L[be];
+    }
+    double d = val[di];
+    for (int p = r0; p < di; ++p) d -= L[p] * L[p];
+    if (!(d > 0.0) || !isfinite(d)) atomicMin(bad, i);
+    L[di] = sqrt(d);
+}
+
+__global__ __launch_bounds__(64) void k_ic0(const TaskRec *__restrict__ tasks,
+                                            const Chunk *__restrict__ chunks,
+                                            const uint32_t *__restrict__ meta, int task_base,
+                                            int ntasks_color, const int *__restrict__ rowptr,
+                                            const int *__restrict__ col, const double *__restrict__ val,
+                                            const int *__restrict__ dpos, double *__restrict__ L, int *bad) {
+    const int local = xcd_remap(blockIdx.x, gridDim.x);
+    if (local >= ntasks_color) return;
+    const TaskRec tr = tasks[task_base + local];
+    const int t = static_cast<int>(threadIdx.x);
+    for (int q = tr.c0; q < tr.c1; ++q) {
+        const Chunk ch = q == tr.c0 ? tr.first : chunks[q];
+        const int nr = ch.shape & 0xffff;
+        const int i = ch.row0 + t;
+        const int lev = t < nr ? static_cast<int>(meta[i] >> kMetaLevelShift) : -1;
+        for (int lv = 0; lv < ch.depth; ++lv) {
+            if (lev == lv) ic0_row(i, rowptr, col, val, dpos, L, bad);
+            // the next level's rows (and the next chunk) read these entries
+            // from memory: this wavefront's stores complete first
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+            __builtin_amdgcn_wave_barrier();
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // substitution sweep over the tasks of one color
 // ---------------------------------------------------------------------------
@@ -2182,6 +2252,7 @@ void iccg_default_options(iccg_options *opt) {
     opt->sweep_grid = 0;
     opt->flow_tail = 0;
     opt->wide_blocks = 1;
+    opt->host_factor = 0;
 }
 
 const char *iccg_strerror(int st) {
@@ -2258,17 +2329,38 @@ void iccg_destroy(iccg_ctx *c) {
 int ic0_factor(iccg_ctx *c, int *breakdown_row) {
     return entry(c, [&]() -> int {
         if (breakdown_row) *breakdown_row = -1;
+        int row = -1;
         std::vector<double> lv;
-        const int row = ic0_host(c->n, c->h_rowptr.data(), c->h_col.data(), c->h_val.data(),
-                                 c->h_dpos.data(), lv);
+        if (c->opt.host_factor) {
+            row = ic0_host(c->n, c->h_rowptr.data(), c->h_col.data(), c->h_val.data(), c->h_dpos.data(), lv);
+            if (row < 0)
+                HIP_CHECK(hipMemcpyAsync(c->lval.p, lv.data(), sizeof(double) * lv.size(), hipMemcpyHostToDevice,
+                                         c->work));
+        } else {
+            // the forward sweep's schedule, color by color
+            hipLaunchKernelGGL(k_fill, dim3(grid_for(c->nnz, kVecThreads, kMaxVecBlocks)), dim3(kVecThreads), 0,
+                               c->work, c->nnz, c->lval.p, 0.0);
+            hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, c->work, c->dint.p, INT_MAX);
+            const DevSweep &d = c->fwd;
+            for (int col = 0; col < c->ncolors; ++col) {
+                const int t0 = d.color_task_ptr[col], t1 = d.color_task_ptr[col + 1];
+                if (t1 == t0) continue;
+                hipLaunchKernelGGL(k_ic0, dim3(t1 - t0), dim3(64), 0, c->work, d.tasks.p, d.chunks.p, d.meta.p,
+                                   t0, t1 - t0, c->rowptr.p, c->col.p, c->val.p, c->dpos.p, c->lval.p, c->dint.p);
+            }
+            HIP_CHECK(hipGetLastError());
+            int bad = INT_MAX;
+            HIP_CHECK(hipMemcpyAsync(&bad, c->dint.p, sizeof(int), hipMemcpyDeviceToHost, c->work));
+            HIP_CHECK(hipStreamSynchronize(c->work));
+            row = bad == INT_MAX ? -1 : bad;
+        }
         if (row >= 0) {
             c->has_factor = false;
             if (breakdown_row) *breakdown_row = row;
             return set_error(ICCG_EBREAKDOWN, "IC(0) pivot not positive at row " + std::to_string(row));
         }
-        HIP_CHECK(hipMemcpyAsync(c->lval.p, lv.data(), sizeof(double) * lv.size(), hipMemcpyHostToDevice, c->work));
         if (!c->lval0.p) ICCG_CHECK(c->lval0.alloc(c->nnz));
-        HIP_CHECK(hipMemcpyAsync(c->lval0.p, lv.data(), sizeof(double) * lv.size(), hipMemcpyHostToDevice, c->work));
+        HIP_CHECK(hipMemcpyAsync(c->lval0.p, c->lval.p, sizeof(double) * c->nnz, hipMemcpyDeviceToDevice, c->work));
         c->has_ic0 = true;
         ICCG_CHECK(install_factor(c));
         HIP_CHECK(hipStreamSynchronize(c->work));   // lv is released on return

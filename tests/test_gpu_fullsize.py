@@ -109,9 +109,10 @@ def test_poisson128_abmc_orderings_bit_exact(s):
 
 
 def test_poisson128_factor(poisson):
+    """The device IC(0) (the context's default) equals the oracle's bit for bit."""
     A, b, o, Ap, lval, ctx = poisson
     got = ctx.get_factor()
-    assert np.max(np.abs(got - lval)) <= 1e-14 * np.max(np.abs(lval))
+    assert np.array_equal(got, lval)
 
 
 def test_poisson128_substitutions(poisson):
@@ -206,6 +207,7 @@ def test_knn1m_leiden_cpm_apply_and_solve(knn):
     want = oracle.ic_apply(Ap, lval, r)
     with iccg.Context(rp, cl, vl, o.block_ptr, o.color_ptr) as ctx:
         ctx.ic0_factor()
+        assert np.array_equal(ctx.get_factor(), lval)     # device IC(0), bit for bit
         zd = torch.zeros(A.n, dtype=torch.float64, device="cuda")
         ctx.ic_apply(_dev(r), zd)
         err = _rel_inf(_host(zd), want)

@@ -101,11 +101,15 @@ def _ids(c):
 
 @pytest.mark.parametrize("case", CASES, ids=_ids)
 def test_factor_matches_oracle(case):
+    """The device factorization (over the forward sweep's schedule, no fused
+    multiply-adds) and the host one both equal the oracle's IC(0) bit for
+    bit."""
     cs = _case(*case)
-    with _ctx(cs) as ctx:
-        got = ctx.get_factor()
     lval = cs[5]
-    assert np.max(np.abs(got - lval)) <= 1e-14 * np.max(np.abs(lval))
+    for host in (False, True):
+        with _ctx(cs, host_factor=host) as ctx:
+            got = ctx.get_factor()
+        assert np.array_equal(got, lval), host
 
 
 @pytest.mark.parametrize("case", CASES, ids=_ids)
@@ -297,6 +301,28 @@ def test_breakdown_reported():
         with pytest.raises(iccg.IccgError) as e:
             ctx.ic_apply(_dev([1.0, 1, 1]), torch.zeros(3, dtype=torch.float64, device="cuda"))
         assert e.value.status == iccg.ICCG_ESTATE
+
+
+@pytest.mark.parametrize("host", [False, True])
+def test_breakdown_row_matches_oracle(host):
+    """A pivot forced non-positive in the middle of the 16^3 matrix: the
+    device factorization (rows of a color in parallel) reports the same first
+    failing row as the serial oracle."""
+    cs = _case("poisson7_16", "abmc", 8)
+    Ap = cs[4]
+    val = Ap.val.copy()
+    i0 = Ap.n // 2 + 3
+    d = [k for k in range(Ap.rowptr[i0], Ap.rowptr[i0 + 1]) if Ap.col[k] == i0][0]
+    val[d] = 1e-3                 # far below the sum of its row's squared factor entries
+    bad = type(Ap)(Ap.n, Ap.rowptr, Ap.col, val)
+    _, want = oracle.ic0(bad)
+    assert 0 <= want
+    o = cs[2]
+    with iccg.Context(bad.rowptr, bad.col, bad.val, o.block_ptr, o.color_ptr, host_factor=host) as ctx:
+        with pytest.raises(iccg.IccgError) as e:
+            ctx.ic0_factor()
+        assert e.value.status == iccg.ICCG_EBREAKDOWN
+        assert e.value.row == want
 
 
 def test_set_factor_roundtrip_and_guard():
