@@ -641,6 +641,39 @@ def main():
                             "speedup_vs_single_solves": round(1e3 * t_single / tmulti, 3),
                             "iters": [int(v) for v in rm["iters"]], "single_iters": single_iters,
                             "max_relres_true": float(np.max(rm["relres_true"]))}
+        # the preconditioner on its own: one block application (forward and
+        # backward sweeps over k columns, the schedule read once) against one
+        # single-column application; algorithmic bytes = the two schedules
+        # (12 nnz_L + 12 n + 4 each) + 32 n per column (r in, y out, y in,
+        # z out), so the intensity grows with k
+        Rk = torch.tensor(rng.standard_normal((k, A.n)), device=dev)
+        Zk = torch.empty_like(Rk)
+        z1 = torch.empty(A.n, dtype=torch.float64, device=dev)
+
+        def _per_call_us(fn, reps=20):
+            fn()
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                fn()
+            e1.record()
+            torch.cuda.synchronize()
+            return 1e3 * e0.elapsed_time(e1) / reps
+
+        us_block = _per_call_us(lambda: ctx.ic_apply_multi(Rk, Zk))
+        us_single = _per_call_us(lambda: ctx.ic_apply(Rk[0], z1))
+        nnz_l = (A.nnz - A.n) // 2
+        by_block = 2 * (12 * nnz_l + 12 * A.n + 4) + 32 * A.n * k
+        by_single = 2 * (12 * nnz_l + 28 * A.n + 4)
+        out["multi_rhs"]["ic_apply"] = {
+            "block_us": round(us_block, 1), "single_us": round(us_single, 1),
+            "per_column_us": round(us_block / k, 1),
+            "block_GBps": round(by_block / us_block / 1e3, 1),
+            "single_GBps": round(by_single / us_single / 1e3, 1),
+            "block_frac": round(by_block / us_block / 1e3 / HBM_PEAK_GBS, 4),
+            "single_frac": round(by_single / us_single / 1e3 / HBM_PEAK_GBS, 4),
+            "bytes_block": int(by_block), "bytes_single": int(by_single)}
         log(f"[bench] multi-RHS: {out['multi_rhs']}")
 
     if not args.no_leiden and not args.no_studies:

@@ -640,8 +640,6 @@ enum SweepMode : int { SW_APPLY = 0, SW_CG_FWD = 1, SW_DOT_BWD = 2 };
 
 // Tasks (wavefronts) per workgroup of a per-color sweep launch.
 constexpr int kSweepWaves = 1;
-// Launches of at least this many tasks read the schedule non-temporally.
-constexpr int kStreamTasks = 1024;
 // Hybrid sweeps run the small trailing colors, up to this many tasks in all,
 // as one dataflow launch (measured on 128^3: 700 beats 100 and 2200).
 constexpr int kFlowTailTasks = 700;
@@ -746,14 +744,15 @@ struct RowRegs {
     F dinv;
 };
 
-// Load phase of a chunk: every independent load at once, so they overlap.  A
-// large launch streams its schedule through once (non-temporal: it should
-// not push the gathered values out of L2); a small one reads it normally, so
-// it can stay cached between sweeps.
+// Load phase of a chunk: every independent load at once, so they overlap.
+// The schedule is read with ordinary loads.  Non-temporal ones were measured
+// slower on every matrix once the slots became jagged (kNN graph and 27-point
+// stencil solves 11-12 % slower, 7-point 0.5 %), although they do help the
+// SpMV's matrix stream.
 template <typename F, int KMAX>
 __device__ __forceinline__ void sweep_load(const Chunk &ch, const uint32_t *__restrict__ meta,
                                            const int *__restrict__ scol, const F *__restrict__ sval,
-                                           const F *__restrict__ inv, bool stream, RowRegs<F, KMAX> &R) {
+                                           const F *__restrict__ inv, RowRegs<F, KMAX> &R) {
     const int t = static_cast<int>(threadIdx.x) & (kChunkRows - 1);
     const int nr = ch.shape & 0xffff, W = ch.shape >> 16;
     const bool jagged = W <= kJaggedMaxWidth;
@@ -762,37 +761,20 @@ __device__ __forceinline__ void sweep_load(const Chunk &ch, const uint32_t *__re
     R.dinv = F(0);
     if (t < nr) {
         int sk = ch.off + t;
-        if (stream) {
 #pragma unroll
-            for (int k = 0; k < KMAX; ++k)
-                if (k < W) {
-                    const int rows_k = slot_rows(ch, k, jagged, nr);
-                    R.vv[k] = F(0);
-                    R.cc[k] = -1;
-                    if (t < rows_k) {
-                        R.vv[k] = __builtin_nontemporal_load(sval + sk);
-                        R.cc[k] = __builtin_nontemporal_load(scol + sk);
-                    }
-                    sk += rows_k;
+        for (int k = 0; k < KMAX; ++k)
+            if (k < W) {
+                const int rows_k = slot_rows(ch, k, jagged, nr);
+                R.vv[k] = F(0);
+                R.cc[k] = -1;
+                if (t < rows_k) {
+                    R.vv[k] = sval[sk];
+                    R.cc[k] = scol[sk];
                 }
-            R.m = __builtin_nontemporal_load(meta + i);
-            R.dinv = __builtin_nontemporal_load(inv + i);
-        } else {
-#pragma unroll
-            for (int k = 0; k < KMAX; ++k)
-                if (k < W) {
-                    const int rows_k = slot_rows(ch, k, jagged, nr);
-                    R.vv[k] = F(0);
-                    R.cc[k] = -1;
-                    if (t < rows_k) {
-                        R.vv[k] = sval[sk];
-                        R.cc[k] = scol[sk];
-                    }
-                    sk += rows_k;
-                }
-            R.m = meta[i];
-            R.dinv = inv[i];
-        }
+                sk += rows_k;
+            }
+        R.m = meta[i];
+        R.dinv = inv[i];
     }
 }
 
@@ -895,11 +877,11 @@ __device__ __forceinline__ void sweep_chunk(const Chunk &ch, const uint32_t *__r
                                             const TIn *__restrict__ in, TOut *__restrict__ out,
                                             const CgArgs &cg, double alpha, F *ys, double &dacc,
                                             const Wait &wait, const Mem &mem, F &y_out,
-                                            uint32_t &m_out, bool stream) {
+                                            uint32_t &m_out) {
     // the first dependency a lane waits for, ahead of the chunk's loads
     const int pre = wait.pre();
     RowRegs<F, KMAX> R;
-    sweep_load<F, KMAX>(ch, meta, scol, sval, inv, stream, R);
+    sweep_load<F, KMAX>(ch, meta, scol, sval, inv, R);
     sweep_finish<F, FWD, KMAX, MODE, TIn, TOut>(ch, R, scol, sval, in, out, cg, alpha, ys, dacc, wait, pre,
                                                 mem, y_out, m_out);
 }
@@ -912,13 +894,13 @@ __device__ __forceinline__ void sweep_task(const TaskRec &tr, const Chunk *__res
                                            const int *__restrict__ scol, const F *__restrict__ sval,
                                            const F *__restrict__ inv, const TIn *__restrict__ in,
                                            TOut *__restrict__ out, const CgArgs &cg, F *ys,
-                                           bool stream, double *part_out) {
+                                           double *part_out) {
     const double alpha = (MODE == SW_CG_FWD) ? cg.sc->alpha : 0.0;
     double dacc = 0.0;
     F yv;
     uint32_t m;
     sweep_chunk<F, FWD, KMAX, MODE, TIn, TOut>(tr.first, meta, scol, sval, inv, in, out, cg, alpha,
-                                               ys, dacc, NoWait(), PlainMem(), yv, m, stream);
+                                               ys, dacc, NoWait(), PlainMem(), yv, m);
     const int nchunks = tr.c1 - tr.c0;
     for (int q = 1; q < nchunks; ++q) {
         // later chunks of this task read earlier chunks' results from memory:
@@ -928,7 +910,7 @@ __device__ __forceinline__ void sweep_task(const TaskRec &tr, const Chunk *__res
         __builtin_amdgcn_wave_barrier();
         const Chunk ch = chunks[FWD ? tr.c0 + q : tr.c1 - 1 - q];
         sweep_chunk<F, FWD, KMAX, MODE, TIn, TOut>(ch, meta, scol, sval, inv, in, out, cg, alpha,
-                                                   ys, dacc, NoWait(), PlainMem(), yv, m, stream);
+                                                   ys, dacc, NoWait(), PlainMem(), yv, m);
     }
     if (MODE != SW_APPLY) {
         const double tsum = wave_sum(dacc);
@@ -967,7 +949,7 @@ __global__ __launch_bounds__(64 * kSweepWaves) void k_sweep(const TaskRec *__res
     const TaskRec tr = tasks[task];
     if (tr.wide >= 0) return;   // run by k_sweep_wide
     sweep_task<F, FWD, KMAX, MODE, TIn, TOut>(tr, chunks, meta, scol, sval, inv, in, out, cg, ys_all[wave],
-                                              ntasks_color >= kStreamTasks, cg.part ? cg.part + task : nullptr);
+                                              cg.part ? cg.part + task : nullptr);
 }
 
 // Block of right-hand sides (columns ld apart): workgroup g runs task g of
@@ -1004,7 +986,7 @@ __global__ __launch_bounds__(64 * kColWaves) void k_sweep_cols(const TaskRec *__
     if (cc.rdot) cc.rdot += off;
     if (cc.sc) cc.sc += c;
     sweep_task<F, FWD, KMAX, MODE, TIn, TOut>(tr, chunks, meta, scol, sval, inv, in ? in + off : nullptr,
-                                              out + off, cc, ys_all[w], false,
+                                              out + off, cc, ys_all[w],
                                               cg.part ? cg.part + static_cast<size_t>(c) * part_ld + task
                                                       : nullptr);
 }
@@ -1221,7 +1203,6 @@ __global__ __launch_bounds__(64) void k_sweep_flow(const TaskRec *__restrict__ t
     const int word = (epoch << 4) | xcc;
     const __amdgpu_buffer_rsrc_t rs_out = make_rsrc(out, static_cast<long long>(n) * sizeof(TOut));
     const __amdgpu_buffer_rsrc_t rs_loc = make_rsrc(fa.flag_loc, 4LL * fa.ntasks);
-    const bool stream = fa.pos1 - fa.pos0 >= kStreamTasks;
     for (int pos = fa.pos0 + static_cast<int>(blockIdx.x); pos < fa.pos1; pos += gridDim.x) {
         const int task = fa.wg_task[pos];
         const TaskRec tr = tasks[task];
@@ -1233,16 +1214,14 @@ __global__ __launch_bounds__(64) void k_sweep_flow(const TaskRec *__restrict__ t
         uint32_t m;
         sweep_chunk<F, FWD, KMAX, MODE, TIn, TOut>(tr.first, meta, scol, sval, inv, in, out, cg,
                                                    alpha, ys, dacc, wait,
-                                                   FlowMem{rs_out, remote, nchunks == 1}, yv, m,
-                                                   stream);
+                                                   FlowMem{rs_out, remote, nchunks == 1}, yv, m);
         for (int q = 1; q < nchunks; ++q) {
             __builtin_amdgcn_s_waitcnt(0);   // this chunk's stores are complete before they are read
             __syncthreads();
             const Chunk ch = chunks[FWD ? tr.c0 + q : tr.c1 - 1 - q];
             sweep_chunk<F, FWD, KMAX, MODE, TIn, TOut>(ch, meta, scol, sval, inv, in, out, cg, alpha,
                                                        ys, dacc, NoWait(),
-                                                       FlowMem{rs_out, remote, q == nchunks - 1}, yv, m,
-                                                       stream);
+                                                       FlowMem{rs_out, remote, q == nchunks - 1}, yv, m);
         }
         if (MODE != SW_APPLY) {
             const double tsum = wave_sum(dacc);
