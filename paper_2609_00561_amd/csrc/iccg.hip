@@ -1459,6 +1459,7 @@ int launch_sweep_t(iccg_ctx *c, const void *in, void *out, const CgArgs &cg) {
                 case 6: hipLaunchKernelGGL((k_sweep<F, FWD, 6, MODE, TIn, TOut>), grid, block, 0, c->work, SWEEP_ARGS); break;
                 case 8: hipLaunchKernelGGL((k_sweep<F, FWD, 8, MODE, TIn, TOut>), grid, block, 0, c->work, SWEEP_ARGS); break;
                 case 16: hipLaunchKernelGGL((k_sweep<F, FWD, 16, MODE, TIn, TOut>), grid, block, 0, c->work, SWEEP_ARGS); break;
+                case 28: hipLaunchKernelGGL((k_sweep<F, FWD, 28, MODE, TIn, TOut>), grid, block, 0, c->work, SWEEP_ARGS); break;
                 default: hipLaunchKernelGGL((k_sweep<F, FWD, 32, MODE, TIn, TOut>), grid, block, 0, c->work, SWEEP_ARGS); break;
             }
             HIP_CHECK(hipGetLastError());
@@ -1680,6 +1681,7 @@ int upload_sweep(iccg_ctx *c, const SweepPlan &plan, DevSweep &d) {
              : plan.max_width <= 6 ? 6
              : plan.max_width <= 8 ? 8
              : plan.max_width <= 16 ? 16
+             : plan.max_width <= 28 ? 28
                                     : 32;
     d.color_task_ptr = plan.color_task_ptr;
     ICCG_CHECK(d.tasks.upload(plan.tasks.data(), plan.tasks.size(), c->work));
@@ -1992,6 +1994,7 @@ int launch_sweep_cols_t(iccg_ctx *c, int k, const void *in, void *out, const CgA
             case 6: hipLaunchKernelGGL((k_sweep_cols<F, FWD, 6, MODE, TIn, TOut>), grid, block, 0, c->work, COLS_ARGS); break;
             case 8: hipLaunchKernelGGL((k_sweep_cols<F, FWD, 8, MODE, TIn, TOut>), grid, block, 0, c->work, COLS_ARGS); break;
             case 16: hipLaunchKernelGGL((k_sweep_cols<F, FWD, 16, MODE, TIn, TOut>), grid, block, 0, c->work, COLS_ARGS); break;
+            case 28: hipLaunchKernelGGL((k_sweep_cols<F, FWD, 28, MODE, TIn, TOut>), grid, block, 0, c->work, COLS_ARGS); break;
             default: hipLaunchKernelGGL((k_sweep_cols<F, FWD, 32, MODE, TIn, TOut>), grid, block, 0, c->work, COLS_ARGS); break;
         }
 #undef COLS_ARGS
