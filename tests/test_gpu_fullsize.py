@@ -6,10 +6,10 @@ benchmark times (per-color launches, HIP graph batches of 32 iterations).
   application and SpMV element by element against the serial oracle (which
   finishes these single steps in well under a second); the solve to 1e-8
   checked by its true residual recomputed on the host.
-* 13-NN graph Laplacian on 10^6 points: ABMC(32), Leiden-CPM(0.05) and
+* 13-NN graph Laplacian on 10^6 points: ABMC(8, 32), Leiden-CPM(0.05) and
   Leiden-modularity orderings bit-exact; IC application on the Leiden
   orderings element by element; the solves by their true residual.
-* 27-point lognormal(sigma = 2) stencil on 96^3, FP32 form: IC application
+* 27-point lognormal(sigma = 2) stencil on 96^3, ABMC(8), FP32 form: IC application
   against the oracle run on the factor rounded to FP32; the solve by its true
   residual and its distance from the FP64 solve.
 
@@ -190,7 +190,8 @@ def knn():
 
 def test_knn1m_orderings_bit_exact(knn):
     A, _ = knn
-    _same_order(iccg.iccg_order_abmc(A, 32), oracle.order_abmc(A, 32))
+    for s in (8, 32):
+        _same_order(iccg.iccg_order_abmc(A, s), oracle.order_abmc(A, s))
     _same_order(iccg.iccg_order_leiden(A, "modularity", 1.0),
                 oracle.order_leiden(A, "modularity", 1.0))
 
@@ -250,8 +251,8 @@ def test_knn1m_leiden_md_wide_blocks(knn):
 
 def test_stencil27_96_fp32_form():
     A, b = _workload("stencil27_96")
-    o = iccg.iccg_order_abmc(A, 32)
-    _same_order(o, oracle.order_abmc(A, 32))
+    o = iccg.iccg_order_abmc(A, _fullsize.FULL["stencil27_96"])
+    _same_order(o, oracle.order_abmc(A, _fullsize.FULL["stencil27_96"]))
     rp, cl, vl = iccg.iccg_permute(A, o.perm)
     Ap = oracle.permute(A, o.perm)
     lval, brk = oracle.ic0(Ap)
