@@ -314,6 +314,7 @@ WORKLOADS = {
     "stencil27_32": _w_stencil27(32),
     "stencil27_12": _w_stencil27(12),
     "randspd_2k": _w_randspd(2000, 0.03),  # about 60 neighbours per row
+    "randspd6_2k": _w_randspd(2000, 0.003),  # about 6 neighbours per row (rows of 9-16 entries after ordering)
     "lognormal7_32": _w_learned(32),      # learned-form training matrices
     "lognormal7_64": _w_learned(64),
     "lognormal7_128": _w_learned(128),

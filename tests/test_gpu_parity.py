@@ -92,6 +92,7 @@ CASES = [
     ("poisson7_32", "abmc", 16),
     ("randspd_2k", "abmc", 16),    # rows of 40-80 entries: padded chunks, entries beyond KMAX
     ("poisson7_16", "abmc", 1),    # node-level multicoloring: one row per block, depth-1 chunks
+    ("randspd6_2k", "abmc", 16),   # widest rows of 11 (forward) and 16 (backward) entries
 ]
 
 

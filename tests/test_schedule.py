@@ -85,6 +85,7 @@ CASES = [
     ("stencil27_12", "abmc", 32, 64),
     ("poisson7_32", "abmc", 16, 32),
     ("randspd_2k", "abmc", 16, 64),                         # rows of 40-80 entries
+    ("randspd6_2k", "abmc", 16, 64),                        # rows of 9-16 entries
 ]
 
 
@@ -108,9 +109,12 @@ def test_schedule_counts_and_invariants(case):
         assert got["forward"]["padded_chunks"] == got["backward"]["padded_chunks"] == 0
     else:
         assert got["forward"]["padded_chunks"] > 0 and got["backward"]["padded_chunks"] > 0
-    if name.startswith("randspd"):
+    if name == "randspd_2k":
         assert got["forward"]["padded_chunks"] < got["forward"]["chunks"]
         assert got["forward"]["max_width"] > 32
+    if name == "randspd6_2k":
+        # the register tier of 16 slots: widest rows between 9 and 16
+        assert 8 < got["forward"]["max_width"] <= 16 and 8 < got["backward"]["max_width"] <= 16
     # the two triangles hold the same number of entries, so only padding
     # can differ between the directions
     nnz_l = (A.nnz - A.n) // 2
