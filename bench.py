@@ -552,6 +552,28 @@ def main():
                 "traffic": round(traffic) if traffic is not None else None,
                 "bytes_per_launch": round(kernels[dom][3]),
                 "avg_launch_us": round(kernels[dom][2] * 1e3, 3)}
+    if traffic is not None:
+        # the same launch duration against the counted HBM bytes
+        roofline["traffic_GBps"] = round(traffic / (kernels[dom][2] * 1e-3) / 1e9, 1)
+        roofline["traffic_frac"] = round(roofline["traffic_GBps"] / HBM_PEAK_GBS, 4)
+
+    # the preconditioner on its own: 100 back-to-back applications on a fixed
+    # r; algorithmic bytes = two sweeps of 12 nnz_L + 28 n + 4
+    rfix = torch.tensor(np.random.default_rng(args.seed + 7).standard_normal(A.n), device=dev)
+    zfix = torch.empty_like(rfix)
+    ctx.ic_apply(rfix, zfix)
+    torch.cuda.synchronize()
+    ea, eb = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ea.record()
+    for _ in range(100):
+        ctx.ic_apply(rfix, zfix)
+    eb.record()
+    torch.cuda.synchronize()
+    apply_us = 1e3 * ea.elapsed_time(eb) / 100
+    apply_gbs = 2.0 * sweep_bytes / (apply_us * 1e-6) / 1e9
+    ic_apply_entry = {"applies": 100, "us": round(apply_us, 2), "GBps": round(apply_gbs, 1),
+                      "frac": round(apply_gbs / HBM_PEAK_GBS, 4)}
+    log(f"[bench] ic_apply: {ic_apply_entry}")
 
     # IC(0) factorization: on the device (the default) and serially on the host
     rp, cl, vl = iccg.iccg_permute(A, order.perm)
@@ -597,6 +619,7 @@ def main():
         "phases_ms": {k: round(prof[k], 3) for k in ("total_ms", "fwd_ms", "bwd_ms", "spmv_ms",
                                                       "other_ms")},
         "roofline": roofline,
+        "ic_apply": ic_apply_entry,
         "ic0_factor": fac,
         "sweep": sweep,
     }
@@ -788,6 +811,20 @@ def main():
             "cpu_model": model, "nproc": avail, "cpus_on_host": total_cpus,
             "phase_s": [round(v, 3) for v in r.phase_s.tolist()],
         }
+        # the 64x64 Laplacian: whole oracle solves, ten timed runs
+        A1, b1 = synth.workload("laplace2d_64", args.seed)
+        o1 = oracle.order_abmc(A1, 64)
+        A1p = oracle.permute(A1, o1.perm)
+        l1, _ = oracle.ic0(A1p)
+        b1p = np.ascontiguousarray(b1[o1.perm])
+        t1s = []
+        for _ in range(10):
+            t1 = time.perf_counter()
+            r1 = oracle.pcg(A1p, l1, b1p, tol=args.tol, maxit=10000)
+            t1s.append(1e3 * (time.perf_counter() - t1))
+        out["cpu_baseline"]["laplace2d_64_solve_ms"] = {
+            "mean": round(float(np.mean(t1s)), 3), "sd": round(float(np.std(t1s, ddof=1)), 3),
+            "median": round(float(np.median(t1s)), 3), "runs": 10, "iters": int(r1.iters)}
         log(f"[bench] CPU oracle: {per_iter * 1e3:.1f} ms/iter -> {est_ms / 1e3:.1f} s estimated")
     ctx.close()
     print(json.dumps(out), flush=True)
