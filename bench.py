@@ -628,12 +628,22 @@ def main():
     A1, b1 = synth.workload("laplace2d_64", args.seed)
     o1 = iccg.iccg_order_abmc(A1, 64)
     c1 = B.ctx(A1, o1)
-    _, t1s, r1, _ = B.time_solves(c1, b1[o1.perm], 10, 2)
+    _, t1s, r1, x1d = B.time_solves(c1, b1[o1.perm], 10, 2)
     c1.close()
+    x1 = x1d.cpu().numpy()
     t1s = 1e3 * np.asarray(t1s)
     out["laplace2d_64"] = {"ordering": "ABMC s=64", "n_b": o1.nblocks, "n_c": o1.ncolors, "iters": r1["iters"],
                            "ms_mean": round(float(t1s.mean()), 3), "ms_sd": round(float(t1s.std(ddof=1)), 3),
                            "ms_median": round(float(np.median(t1s)), 3), "runs": 10}
+    if not args.no_fp32:
+        # the FP32 form on the same system: time and distance from the FP64 solution
+        c1 = B.ctx(A1, o1, precision="fp32")
+        _, t1f, r1f, x1f = B.time_solves(c1, b1[o1.perm], 10, 2)
+        c1.close()
+        x1f = x1f.cpu().numpy()
+        out["laplace2d_64"]["fp32"] = {
+            "ms_median": round(1e3 * float(np.median(t1f)), 3), "iters": r1f["iters"],
+            "x_rel_diff_vs_fp64": float(np.linalg.norm(x1f - x1) / np.linalg.norm(x1))}
     log(f"[bench] laplace2d_64: {out['laplace2d_64']}")
 
     if not args.no_fp32:
