@@ -12,6 +12,8 @@
 // (or, by option, k_sweep_flow: one dataflow launch for all colors, or for
 // the small ones only)
 //   stopping test on ||r||, beta, rho         k_reduce_rr_beta
+// (inside the loop the last color of both sweeps runs as one k_sweep_turn
+// launch: its forward then its backward substitution, task by task)
 // and after the last iteration x += alpha p   k_axpy_alpha
 // The sweeps give every 64-row chunk of a color one wavefront (one lane per
 // row): the terms whose values were final before the chunk started are
@@ -991,6 +993,34 @@ __global__ __launch_bounds__(64 * kColWaves) void k_sweep_cols(const TaskRec *__
                                                       : nullptr);
 }
 
+// The turn of a CG iteration: the forward and then the backward substitution
+// of the last color's tasks in one launch.  Blocks of one color are not
+// coupled and no row lies in a later color, so the backward half of a task
+// reads only values its own wavefront has just written; both halves are
+// k_sweep's work for the task (the forward and backward schedules pack the
+// color's blocks into the same tasks), so the results are bit-identical to
+// two launches.
+template <typename F, int KMAX>
+__global__ __launch_bounds__(64) void k_sweep_turn(SweepArgs<F> fa, SweepArgs<F> ba, int task_base,
+                                                   int ntasks, F *__restrict__ y, double *__restrict__ z,
+                                                   CgArgs f, CgArgs g) {
+    if (f.sc->done != DONE_RUNNING) return;
+    __shared__ F ys[kChunkRows];
+    const int local = xcd_remap(blockIdx.x, gridDim.x);
+    if (local >= ntasks) return;
+    const int task = task_base + local;
+    const TaskRec tf = fa.tasks[task];
+    sweep_task<F, true, KMAX, SW_CG_FWD, double, F>(tf, fa.chunks, fa.meta, fa.scol, fa.sval, fa.inv, nullptr,
+                                                     y, f, ys, f.part + task);
+    // the backward half reads this wavefront's stores: they complete first
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    const TaskRec tb = ba.tasks[task];
+    sweep_task<F, false, KMAX, SW_DOT_BWD, F, double>(tb, ba.chunks, ba.meta, ba.scol, ba.sval, ba.inv, y, z,
+                                                       g, ys, g.part + task);
+}
+
 // Wide task (see WidePlan): one block of more than 64 rows, run piece by
 // piece by a workgroup of WAVES wavefronts.  Wavefront w takes
 // sub-chunk w of the piece, one lane per row.  Terms from outside the piece
@@ -1419,8 +1449,9 @@ int launch_flow(iccg_ctx *c, DevSweep &d, const SweepArgs<F> &a, int pos0, int p
 //              the forward epoch, the forward dataflow launch the backward
 //              one, so no launch is added (a backward sweep on its own gets
 //              its bump from the entry point).
+// turn: the last color is left to k_sweep_turn (per-color launches only).
 template <typename F, bool FWD, int MODE>
-int launch_sweep_t(iccg_ctx *c, const void *in, void *out, const CgArgs &cg) {
+int launch_sweep_t(iccg_ctx *c, const void *in, void *out, const CgArgs &cg, bool turn = false) {
     using TIn = typename std::conditional<FWD, double, F>::type;
     using TOut = typename std::conditional<FWD, F, double>::type;
     DevSweep &d = FWD ? c->fwd : c->bwd;
@@ -1480,8 +1511,9 @@ int launch_sweep_t(iccg_ctx *c, const void *in, void *out, const CgArgs &cg) {
         }
         return ICCG_OK;
     };
+    const int skip = (turn && tail_tasks == 0) ? 1 : 0;
     if (FWD) {
-        for (int col = 0; col < tail; ++col)
+        for (int col = 0; col < tail - skip; ++col)
             ICCG_CHECK(per_color(col, col == 0 && tail_tasks > 0 ? d.epoch.p : nullptr));
         if (tail_tasks > 0) {
             if (tail == 0)
@@ -1498,7 +1530,7 @@ int launch_sweep_t(iccg_ctx *c, const void *in, void *out, const CgArgs &cg) {
             ICCG_CHECK((launch_flow<F, FWD, MODE>(c, d, a, 0, tail_tasks, 0, nullptr, pin, pout, cg)));
             ++launched;
         }
-        for (int col = tail - 1; col >= 0; --col) ICCG_CHECK(per_color(col, nullptr));
+        for (int col = tail - 1 - skip; col >= 0; --col) ICCG_CHECK(per_color(col, nullptr));
     }
 #undef SWEEP_ARGS
 #undef WIDE_ARGS
@@ -1548,9 +1580,48 @@ int flow_guard(iccg_ctx *c, long long sweeps) {
 }
 
 template <bool FWD, int MODE>
-int launch_sweep(iccg_ctx *c, const void *in, void *out, const CgArgs &cg) {
-    return c->fp32() ? launch_sweep_t<float, FWD, MODE>(c, in, out, cg)
-                     : launch_sweep_t<double, FWD, MODE>(c, in, out, cg);
+int launch_sweep(iccg_ctx *c, const void *in, void *out, const CgArgs &cg, bool turn = false) {
+    return c->fp32() ? launch_sweep_t<float, FWD, MODE>(c, in, out, cg, turn)
+                     : launch_sweep_t<double, FWD, MODE>(c, in, out, cg, turn);
+}
+
+void *ytmp(iccg_ctx *c);
+
+// The last color of the CG sweeps in one k_sweep_turn launch: per-color
+// launches, no wide task in that color, the same task packing both ways, and
+// not inside an instrumented solve (whose per-sweep times it would mix).
+bool turn_ok(const iccg_ctx *c) {
+    if (c->opt.sweep_launch != 0 || c->prof || c->ncolors < 1) return false;
+    if (c->fwd.color_task_ptr != c->bwd.color_task_ptr) return false;
+    const int last = c->ncolors - 1;
+    for (const DevSweep *d : {&c->fwd, &c->bwd}) {
+        const DevWide &w = d->wide;
+        if (w.nwide > 0 && w.color_ptr[last + 1] > w.color_ptr[last]) return false;
+    }
+    return true;
+}
+
+template <typename F>
+int launch_turn_t(iccg_ctx *c, const CgArgs &f, const CgArgs &g) {
+    const int last = c->ncolors - 1;
+    const int t0 = c->fwd.color_task_ptr[last], nt = c->fwd.color_task_ptr[last + 1] - t0;
+    if (nt <= 0) return ICCG_OK;
+    const SweepArgs<F> fa = sweep_args<F>(c, c->fwd), ba = sweep_args<F>(c, c->bwd);
+    F *y = static_cast<F *>(ytmp(c));
+    const int K = std::max(c->fwd.kmax, c->bwd.kmax);
+    const dim3 grid(nt), block(64);
+#define TURN_ARGS fa, ba, t0, nt, y, c->z.p, f, g
+    switch (K) {
+        case 4: hipLaunchKernelGGL((k_sweep_turn<F, 4>), grid, block, 0, c->work, TURN_ARGS); break;
+        case 6: hipLaunchKernelGGL((k_sweep_turn<F, 6>), grid, block, 0, c->work, TURN_ARGS); break;
+        case 8: hipLaunchKernelGGL((k_sweep_turn<F, 8>), grid, block, 0, c->work, TURN_ARGS); break;
+        case 16: hipLaunchKernelGGL((k_sweep_turn<F, 16>), grid, block, 0, c->work, TURN_ARGS); break;
+        case 28: hipLaunchKernelGGL((k_sweep_turn<F, 28>), grid, block, 0, c->work, TURN_ARGS); break;
+        default: hipLaunchKernelGGL((k_sweep_turn<F, 32>), grid, block, 0, c->work, TURN_ARGS); break;
+    }
+#undef TURN_ARGS
+    HIP_CHECK(hipGetLastError());
+    return ICCG_OK;
 }
 
 CgArgs no_cg() {
@@ -1589,12 +1660,14 @@ int enqueue_iteration(iccg_ctx *c, long long j) {
     f.q = c->q.p;
     f.part = c->part_rr.p;
     f.sc = sc;
-    ICCG_CHECK((launch_sweep<true, SW_CG_FWD>(c, nullptr, ytmp(c), f)));
     CgArgs g = no_cg();
     g.rdot = c->r.p;
     g.part = c->part.p;
     g.sc = sc;
-    ICCG_CHECK((launch_sweep<false, SW_DOT_BWD>(c, ytmp(c), c->z.p, g)));
+    const bool turn = turn_ok(c);
+    ICCG_CHECK((launch_sweep<true, SW_CG_FWD>(c, nullptr, ytmp(c), f, turn)));
+    if (turn) ICCG_CHECK(c->fp32() ? launch_turn_t<float>(c, f, g) : launch_turn_t<double>(c, f, g));
+    ICCG_CHECK((launch_sweep<false, SW_DOT_BWD>(c, ytmp(c), c->z.p, g, turn)));
     hipLaunchKernelGGL(k_reduce_rr_beta, dim3(1), dim3(kReduceThreads), 0, c->work, c->part_rr.p,
                        c->fwd.ntasks, c->part.p, c->bwd.ntasks, sc, c->hist.p, 0, 0);
     HIP_CHECK(hipGetLastError());
