@@ -243,7 +243,10 @@ def traffic_run(args):
     s = int(args.block_sizes.split(",")[0])
     order = iccg.iccg_order_abmc(A, s)
     rp, cl, vl = iccg.iccg_permute(A, order.perm)
-    with iccg.Context(rp, cl, vl, order.block_ptr, order.color_ptr) as ctx:
+    # --unfused: the last color's sweeps as two launches, so the counted
+    # forward-sweep dispatches are the n_c per-color launches the roofline's
+    # instrumented solve times
+    with iccg.Context(rp, cl, vl, order.block_ptr, order.color_ptr, fuse_turn=not args.unfused) as ctx:
         ctx.ic0_factor()
         bd = torch.tensor(b[order.perm], device="cuda")
         xd = torch.zeros(A.n, dtype=torch.float64, device="cuda")
@@ -283,6 +286,8 @@ def parse():
     ap.add_argument("--learned-seeds", type=int, default=3,
                     help="unseen seeds per sigma in {0.5, 1, 2} and per grid (64^3, 128^3)")
     ap.add_argument("--seed", type=int, default=42)
+    ap.add_argument("--unfused", action="store_true",
+                    help="with --traffic-run: the last color's two sweeps as separate launches")
     ap.add_argument("--traffic-run", action="store_true",
                     help="run only the program profiled by the --pmc traffic passes")
     ap.add_argument("--traffic-summary", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "CMD_FETCH", "CMD_WRITE"),

@@ -99,9 +99,12 @@ typedef struct {
     int   host_factor;  /* ic0_factor on the device over the forward sweep's
                            schedule (0, default) or serially on the host (1);
                            both give the serial FP64 factorization bit for bit */
+    int   fuse_turn;    /* per-color sweeps inside iccg_solve: the last color's
+                           forward and backward substitutions in one launch, task
+                           by task (1, default; bit-identical), or in two (0)  */
 } iccg_options;
 
-/* Fills *opt with the defaults above (FP64, null stream, 32, 64, 1, 0, 0, 0, 1, 0). */
+/* Fills *opt with the defaults above (FP64, null stream, 32, 64, 1, 0, 0, 0, 1, 0, 1). */
 void iccg_default_options(iccg_options *opt);
 
 /* ------------------------------------------------------------------------ */

@@ -1591,7 +1591,7 @@ void *ytmp(iccg_ctx *c);
 // launches, no wide task in that color, the same task packing both ways, and
 // not inside an instrumented solve (whose per-sweep times it would mix).
 bool turn_ok(const iccg_ctx *c) {
-    if (c->opt.sweep_launch != 0 || c->prof || c->ncolors < 1) return false;
+    if (!c->opt.fuse_turn || c->opt.sweep_launch != 0 || c->prof || c->ncolors < 1) return false;
     if (c->fwd.color_task_ptr != c->bwd.color_task_ptr) return false;
     const int last = c->ncolors - 1;
     for (const DevSweep *d : {&c->fwd, &c->bwd}) {
@@ -2308,6 +2308,7 @@ void iccg_default_options(iccg_options *opt) {
     opt->flow_tail = 0;
     opt->wide_blocks = 1;
     opt->host_factor = 0;
+    opt->fuse_turn = 1;
 }
 
 const char *iccg_strerror(int st) {

@@ -60,7 +60,8 @@ class _Options(ctypes.Structure):
                 ("check_every", ctypes.c_int), ("pack_rows", ctypes.c_int),
                 ("use_graph", ctypes.c_int), ("sweep_launch", ctypes.c_int),
                 ("sweep_grid", ctypes.c_int), ("flow_tail", ctypes.c_int),
-                ("wide_blocks", ctypes.c_int), ("host_factor", ctypes.c_int)]
+                ("wide_blocks", ctypes.c_int), ("host_factor", ctypes.c_int),
+                ("fuse_turn", ctypes.c_int)]
 
 
 class _Info(ctypes.Structure):
@@ -255,7 +256,7 @@ class Context:
     def __init__(self, rowptr, col, val, block_ptr, color_ptr, precision: str = "fp64",
                  stream=None, check_every: int = 32, pack_rows: int = 64, use_graph: bool = True,
                  sweep_launch: str = "per_color", sweep_grid: int = 0, flow_tail: int = 0,
-                 wide_blocks: bool = True, host_factor: bool = False):
+                 wide_blocks: bool = True, host_factor: bool = False, fuse_turn: bool = True):
         import torch
         lib = load()
         opt = _Options()
@@ -272,6 +273,7 @@ class Context:
         opt.flow_tail = int(flow_tail)
         opt.wide_blocks = 1 if wide_blocks else 0
         opt.host_factor = 1 if host_factor else 0
+        opt.fuse_turn = 1 if fuse_turn else 0
         self._keep = [_host_i32(rowptr), _host_i32(col), _host_f64(val), _host_i32(block_ptr),
                       _host_i32(color_ptr)]
         rp, cl, vl, bp, cp = self._keep

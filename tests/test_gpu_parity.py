@@ -236,6 +236,23 @@ def test_graph_and_eager_identical():
         assert np.array_equal(x, outs[0][1])
 
 
+@pytest.mark.parametrize("case", [CASES[0], CASES[1], CASES[5], CASES[8]], ids=_ids)
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_turn_fusion_identical(case, precision):
+    """The last color's forward and backward substitutions in one launch give
+    the two-launch solve bit for bit (iterations, history, solution)."""
+    cs = _case(*case)
+    outs = []
+    for fuse in (False, True):
+        with _ctx(cs, precision=precision, fuse_turn=fuse) as ctx:
+            xd = torch.zeros(cs[0].n, dtype=torch.float64, device="cuda")
+            res = ctx.solve(_dev(cs[6]), xd, tol=1e-8, maxit=5000)
+            outs.append((res["iters"], ctx.residual_history(), _host(xd)))
+    assert outs[0][0] == outs[1][0]
+    assert np.array_equal(np.asarray(outs[0][1]), np.asarray(outs[1][1]))
+    assert np.array_equal(outs[0][2], outs[1][2])
+
+
 def test_repeated_solves_deterministic():
     cs = _case("knn13_20k", "abmc", 32)
     Ap, bp = cs[4], cs[6]
