@@ -2,7 +2,10 @@
 
 Host-only C++ (ordering, schedules, host IC(0)) is compiled with g++ and
 -ffp-contract=off so the ordering arithmetic is reproducible; the HIP sources
-are compiled with hipcc for gfx950 with packed-FP32 instructions disabled.
+are compiled with hipcc for gfx950 with packed-FP32 instructions disabled and
+kernel arguments preloaded into scalar registers (the leading 56 bytes of a
+launch's arguments are in registers when a wavefront starts; the kernels put
+the arguments they read first at the front).
 
 Run as ``python -m paper_2609_00561_amd.build``.
 """
@@ -41,6 +44,7 @@ def build(verbose: bool = True) -> str:
         obj = os.path.join(BUILD, src + ".o")
         _run(["hipcc", "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
               "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+              "-mllvm", "-amdgpu-kernarg-preload-count=16",
               "-Wno-unused-command-line-argument",
               "-I", INCLUDE, "-I", CSRC, "-c", os.path.join(CSRC, src), "-o", obj])
         objs.append(obj)

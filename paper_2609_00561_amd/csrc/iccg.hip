@@ -78,6 +78,16 @@ __device__ inline int xcd_remap(int b, int G) {
     return x * q + min(x, r) + i;
 }
 
+// The stopping flag a launch tests before its work: the solve's, or, for a
+// launch outside a solve (no scalar block), one that always reads
+// DONE_RUNNING.  Reading it through a selected pointer keeps the load free of
+// a branch, so it is issued together with the launch's first other loads and
+// the launch waits for one memory round trip, not two in a row.
+__device__ int g_running = DONE_RUNNING;   // never written
+__device__ __forceinline__ const int *done_flag(const DevScalars *sc) {
+    return sc ? &sc->done : &g_running;
+}
+
 // ---------------------------------------------------------------------------
 // reductions
 // ---------------------------------------------------------------------------
@@ -103,21 +113,24 @@ __device__ inline double block_sum(double v) {
 
 // Thread t's share of a fixed-order sum over part[0, np): pairs (2i, 2i+1)
 // for i = t, t + NT, ... in that order, loaded 16 bytes at a time with up to
-// 16 pairs in flight, so one workgroup covers 32K partials in one round trip.
+// kPartialRound pairs in flight, so one workgroup of 1024 threads covers 40K
+// partials in one round trip (a sweep's 32K tasks and a few more: 16 pairs
+// per thread left the last handful of partials to a second round trip).
+constexpr int kPartialRound = 20;
 template <int NT>
 __device__ __forceinline__ double thread_partial(const double *__restrict__ part, int np) {
     const int npair = np >> 1;
     const double2 *p2 = reinterpret_cast<const double2 *>(part);
     double v = 0.0;
-    for (int base = 0; base < npair; base += 16 * NT) {
-        double2 buf[16];
+    for (int base = 0; base < npair; base += kPartialRound * NT) {
+        double2 buf[kPartialRound];
 #pragma unroll
-        for (int u = 0; u < 16; ++u) {
+        for (int u = 0; u < kPartialRound; ++u) {
             const int i = base + u * NT + static_cast<int>(threadIdx.x);
             buf[u] = i < npair ? p2[i] : make_double2(0.0, 0.0);
         }
 #pragma unroll
-        for (int u = 0; u < 16; ++u) v += buf[u].x + buf[u].y;
+        for (int u = 0; u < kPartialRound; ++u) v += buf[u].x + buf[u].y;
     }
     if ((np & 1) && threadIdx.x == 0) v += part[np - 1];
     return v;
@@ -135,10 +148,13 @@ __global__ __launch_bounds__(kReduceThreads) void k_reduce(const double *__restr
     sc += col;
     hist += static_cast<size_t>(col) * hist_ld;
     if (out) out += col;
-    if (op != OP_STORE && op != OP_TRUE && op != OP_BNORM && sc->done != DONE_RUNNING) return;
+    // the stopping flag is read together with the partials and tested after
+    // the sum (only thread 0 writes), so the launch waits for one round trip
+    const bool stopped = sc->done != DONE_RUNNING;
     double v = thread_partial<kReduceThreads>(part, np);
     v = block_sum<kReduceThreads>(v);
     if (threadIdx.x != 0) return;
+    if (op != OP_STORE && op != OP_TRUE && op != OP_BNORM && stopped) return;
     switch (op) {
         case OP_STORE: out[0] = v; break;
         case OP_BNORM: sc->bnorm = (v > 0.0) ? sqrt(v) : 1.0; break;
@@ -197,13 +213,14 @@ __global__ __launch_bounds__(kReduceThreads) void k_reduce_rr_beta(const double 
     rz_part += static_cast<size_t>(col) * part_ld;
     sc += col;
     hist += static_cast<size_t>(col) * hist_ld;
-    if (sc->done != DONE_RUNNING) return;
+    // stopping flag read together with the partials, tested by thread 0
+    const bool stopped = sc->done != DONE_RUNNING;
     double a = thread_partial<kReduceThreads>(rr_part, n_rr);
     double b = thread_partial<kReduceThreads>(rz_part, n_rz);
     a = block_sum<kReduceThreads>(a);
     __syncthreads();   // block_sum's scratch is reused
     b = block_sum<kReduceThreads>(b);
-    if (threadIdx.x != 0) return;
+    if (threadIdx.x != 0 || stopped) return;
     const int it = sc->iter + 1;
     sc->iter = it;
     const double rel = sqrt(a) / sc->bnorm;
@@ -239,85 +256,97 @@ __global__ void k_init_scalars(DevScalars *sc, double tol, int maxit, int hist_c
 // ---------------------------------------------------------------------------
 enum SpmvMode : int { SP_PLAIN = 0, SP_RESID = 1 };
 constexpr int kSpmvSlicesPerWave = 2;
+struct alignas(16 * kSpmvSlicesPerWave) SliceRecs {
+    int4 r[kSpmvSlicesPerWave];
+};
 // Columns (wavefronts) per workgroup of the block-of-right-hand-sides kernels.
 constexpr int kColWaves = 8;
 
-// One wavefront per kSpmvSlicesPerWave consecutive launch positions (grid-
-// stride over the slices); WMAX slots of a row are loaded into registers at
-// once, then all gathers, then the row sum in ascending column order.  wg:
-// the wavefront's logical index among G; lane 0 writes the wavefront's
-// partial sum to *part_out.  NT: stream the matrix with non-temporal loads.
+// One wavefront per kSpmvSlicesPerWave consecutive launch positions (the
+// grid has ceil(nslices / kSpmvSlicesPerWave) wavefronts); WMAX slots of a
+// row are loaded into registers at once, then all gathers, then the row sum
+// in ascending column order.  wg: the wavefront's logical index; lane 0
+// writes the wavefront's partial sum to *part_out.  NT: stream the matrix
+// with non-temporal loads.  stop: the solve's stopping flag (the wavefront
+// returns at once unless it reads DONE_RUNNING).
 template <int MODE, int WMAX, bool NT>
 __device__ __forceinline__ void spmv_wave(int n, int nslices, const int4 *__restrict__ slices,
                                           const int *__restrict__ col, const double *__restrict__ val,
                                           const double *__restrict__ x, double *__restrict__ y,
                                           const double *__restrict__ b, double *__restrict__ part_out,
-                                          int wg, int G) {
+                                          int wg, const int *stop) {
     constexpr int U = kSpmvSlicesPerWave;
     const int lane = static_cast<int>(threadIdx.x) & 63;
-    double acc = 0.0;
-    for (int lg0 = wg * U; lg0 < nslices; lg0 += G * U) {
-        // U consecutive launch positions at once, so one wavefront has all of
-        // their loads in flight together.  Launch-ordered slice record:
-        // (slice, first slot, width).
-        int off[U], w[U], row[U];
-        int cc[U][WMAX];
-        double vv[U][WMAX], xv[U][WMAX], own_x[U], own_b[U];
+    const int lg0 = wg * U;
+    // U consecutive launch positions at once, so one wavefront has all of
+    // their loads in flight together.  Launch-ordered slice record:
+    // (slice, first slot, width), padded to a whole number of wavefronts
+    // with empty records.  The records and the stopping flag are loaded
+    // together, so the wavefront waits for one memory round trip before its
+    // matrix loads; a stopped solve leaves every slice with no rows and no
+    // slots, and then nothing else is loaded or stored but the partial sum
+    // (zero).
+    const SliceRecs recs = reinterpret_cast<const SliceRecs *>(slices)[wg];
+    const bool running = *stop == DONE_RUNNING;
+    int off[U], w[U], row[U];
+    int cc[U][WMAX];
+    double vv[U][WMAX], xv[U][WMAX], own_x[U], own_b[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int4 rec = lg0 + u < nslices ? slices[lg0 + u] : make_int4(0, 0, 0, 0);
-            off[u] = rec.y + lane;
-            w[u] = rec.z;
-            row[u] = lg0 + u < nslices ? rec.x * 64 + lane : n;
-        }
-        // the matrix streams through once (non-temporal: it should not push
-        // the gathered vector out of L2), unless several wavefronts read it
+    for (int u = 0; u < U; ++u) {
+        const bool valid = running && lg0 + u < nslices;
+        const int4 rec = recs.r[u];
+        off[u] = rec.y + lane;
+        w[u] = valid ? rec.z : 0;
+        row[u] = valid ? rec.x * 64 + lane : n;
+    }
+    // the matrix streams through once (non-temporal: it should not push
+    // the gathered vector out of L2), unless several wavefronts read it
 #pragma unroll
-        for (int u = 0; u < U; ++u)
+    for (int u = 0; u < U; ++u)
 #pragma unroll
-            for (int k = 0; k < WMAX; ++k)
-                if (k < w[u]) {
-                    if (NT) {
-                        cc[u][k] = __builtin_nontemporal_load(col + off[u] + k * 64);
-                        vv[u][k] = __builtin_nontemporal_load(val + off[u] + k * 64);
-                    } else {
-                        cc[u][k] = col[off[u] + k * 64];
-                        vv[u][k] = val[off[u] + k * 64];
-                    }
-                }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            own_x[u] = 0.0;
-            own_b[u] = 0.0;
-            if (row[u] < n) {
-                own_x[u] = x[row[u]];
-                if (MODE == SP_RESID) own_b[u] = b[row[u]];
-            }
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u)
-#pragma unroll
-            for (int k = 0; k < WMAX; ++k)
-                if (k < w[u]) xv[u][k] = x[cc[u][k] < 0 ? 0 : cc[u][k]];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            double sum = 0.0;
-#pragma unroll
-            for (int k = 0; k < WMAX; ++k)
-                if (k < w[u]) sum = (cc[u][k] >= 0) ? sum + vv[u][k] * xv[u][k] : sum;
-            for (int k = WMAX; k < w[u]; ++k) {
-                const int c = col[off[u] + k * 64];
-                if (c >= 0) sum += val[off[u] + k * 64] * x[c];
-            }
-            if (row[u] < n) {
-                if (MODE == SP_PLAIN) {
-                    y[row[u]] = sum;
-                    acc += own_x[u] * sum;
+        for (int k = 0; k < WMAX; ++k)
+            if (k < w[u]) {
+                if (NT) {
+                    cc[u][k] = __builtin_nontemporal_load(col + off[u] + k * 64);
+                    vv[u][k] = __builtin_nontemporal_load(val + off[u] + k * 64);
                 } else {
-                    const double rv = own_b[u] - sum;
-                    y[row[u]] = rv;
-                    acc += rv * rv;
+                    cc[u][k] = col[off[u] + k * 64];
+                    vv[u][k] = val[off[u] + k * 64];
                 }
+            }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        own_x[u] = 0.0;
+        own_b[u] = 0.0;
+        if (row[u] < n) {
+            own_x[u] = x[row[u]];
+            if (MODE == SP_RESID) own_b[u] = b[row[u]];
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int k = 0; k < WMAX; ++k)
+            if (k < w[u]) xv[u][k] = x[cc[u][k] < 0 ? 0 : cc[u][k]];
+    double acc = 0.0;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        double sum = 0.0;
+#pragma unroll
+        for (int k = 0; k < WMAX; ++k)
+            if (k < w[u]) sum = (cc[u][k] >= 0) ? sum + vv[u][k] * xv[u][k] : sum;
+        for (int k = WMAX; k < w[u]; ++k) {
+            const int c = col[off[u] + k * 64];
+            if (c >= 0) sum += val[off[u] + k * 64] * x[c];
+        }
+        if (row[u] < n) {
+            if (MODE == SP_PLAIN) {
+                y[row[u]] = sum;
+                acc += own_x[u] * sum;
+            } else {
+                const double rv = own_b[u] - sum;
+                y[row[u]] = rv;
+                acc += rv * rv;
             }
         }
     }
@@ -325,18 +354,21 @@ __device__ __forceinline__ void spmv_wave(int n, int nslices, const int4 *__rest
     if ((threadIdx.x & 63) == 0) *part_out = t;
 }
 
+// (sc among the leading, preloaded arguments, as for k_sweep)
 template <int MODE, int WMAX>
 __global__ __launch_bounds__(64) void k_spmv(int n, int nslices, const int4 *__restrict__ slices,
+                                             const DevScalars *sc,
                                              const int *__restrict__ col,
                                              const double *__restrict__ val,
                                              const double *__restrict__ x,
                                              double *__restrict__ y,
                                              const double *__restrict__ b,
-                                             double *__restrict__ part,
-                                             const DevScalars *sc) {
-    if (sc && sc->done != DONE_RUNNING) return;
+                                             double *__restrict__ part) {
+    // the grid is ceil(nslices / kSpmvSlicesPerWave) (computed here rather than
+    // read from the dispatch packet, so the launch's first loads are its own)
+    const int grid = (nslices + kSpmvSlicesPerWave - 1) / kSpmvSlicesPerWave;
     spmv_wave<MODE, WMAX, true>(n, nslices, slices, col, val, x, y, b, part + blockIdx.x,
-                                xcd_remap(blockIdx.x, gridDim.x), gridDim.x);
+                                xcd_remap(blockIdx.x, grid), done_flag(sc));
 }
 
 // Block of right-hand sides (columns ld apart): workgroup g runs the slices
@@ -363,7 +395,7 @@ __global__ __launch_bounds__(64 * kColWaves) void k_spmv_cols(int n, int nslices
     const size_t off = static_cast<size_t>(c) * ld;
     spmv_wave<MODE, WMAX, false>(n, nslices, slices, col, val, x + off, y + off, b ? b + off : nullptr,
                                  part + static_cast<size_t>(c) * part_ld + blockIdx.x,
-                                 xcd_remap(blockIdx.x, gridDim.x), gridDim.x);
+                                 xcd_remap(blockIdx.x, gridDim.x), done_flag(nullptr));
 }
 
 // ---------------------------------------------------------------------------
@@ -388,23 +420,22 @@ __global__ __launch_bounds__(kVecThreads) void k_fill(int n, double *__restrict_
 // x += alpha p (the previous iteration's step, alpha still in the scalar
 // block), then p = z + beta p.  alpha = beta = 0 and p = 0 before the first
 // iteration.
-// Rows are visited slice by slice in the SpMV's launch order and XCD mapping,
-// so the p values each XCD writes are the ones its SpMV workgroups gather.
+// One workgroup per slice (the grid has nslices workgroups), visited in the
+// SpMV's launch order and XCD mapping, so the p values each XCD writes are
+// the ones its SpMV workgroups gather.
 __global__ __launch_bounds__(64) void k_update_p(int n, int nslices,
                                                  const int *__restrict__ slice_order,
                                                  double *__restrict__ x, double *__restrict__ p,
                                                  const double *__restrict__ z,
                                                  const DevScalars *sc) {
-    if (sc->done != DONE_RUNNING) return;
+    // the slice index and the stopping flag are loaded together and tested
+    // at once (one memory round trip before the vector loads)
+    const int i = slice_order[xcd_remap(blockIdx.x, nslices)] * 64 + static_cast<int>(threadIdx.x);
     const double alpha = sc->alpha, beta = sc->beta;
-    const int wg = xcd_remap(blockIdx.x, gridDim.x);
-    for (int lg = wg; lg < nslices; lg += gridDim.x) {
-        const int i = slice_order[lg] * 64 + static_cast<int>(threadIdx.x);
-        if (i < n) {
-            const double pi = p[i];
-            x[i] = x[i] + alpha * pi;
-            p[i] = z[i] + beta * pi;
-        }
+    if ((sc->done == DONE_RUNNING) & (i < n)) {
+        const double pi = p[i];
+        x[i] = x[i] + alpha * pi;
+        p[i] = z[i] + beta * pi;
     }
 }
 
@@ -927,31 +958,40 @@ __device__ __forceinline__ void sweep_task(const TaskRec &tr, const Chunk *__res
 // gathers of values final before the chunk, then the in-chunk terms level by
 // level through LDS.  The per-row subtraction order is: before-chunk terms in
 // ascending column order, then in-chunk terms in ascending column order.
+// The arguments a wavefront needs first lead the list: the library is built
+// with kernel-argument preloading, which puts the leading 56 bytes of a
+// launch's arguments in scalar registers when the wavefront starts, so the
+// task record and the stopping flag are loaded without waiting for them.
 template <typename F, bool FWD, int KMAX, int MODE, typename TIn, typename TOut>
 __global__ __launch_bounds__(64 * kSweepWaves) void k_sweep(const TaskRec *__restrict__ tasks,
-                                                            const Chunk *__restrict__ chunks,
+                                                            const DevScalars *sc,
                                                             const uint32_t *__restrict__ meta,
                                                             const int *__restrict__ scol,
                                                             const F *__restrict__ sval,
                                                             const F *__restrict__ inv, int task_base,
-                                                            int ntasks_color, int *bump,
-                                                            const TIn *__restrict__ in,
+                                                            int ntasks_color,
+                                                            const Chunk *__restrict__ chunks,
+                                                            int *bump, const TIn *__restrict__ in,
                                                             TOut *__restrict__ out, CgArgs cg) {
-    if (cg.sc && cg.sc->done != DONE_RUNNING) return;
-    // bumps the epoch of a dataflow launch that follows in the stream
-    if (bump && blockIdx.x == 0 && threadIdx.x == 0) *bump += 1;
     __shared__ F ys_all[kSweepWaves][kChunkRows];
     // kSweepWaves independent tasks per workgroup, one per wavefront (fewer
     // workgroups to dispatch); consecutive tasks, so the XCD regions hold
     const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) / 64);
     const int nwg = (ntasks_color + kSweepWaves - 1) / kSweepWaves;
     const int local = xcd_remap(blockIdx.x, nwg) * kSweepWaves + wave;
-    if (local >= ntasks_color) return;
-    const int task = task_base + local;
+    // the task record and the stopping flag are read together (a surplus
+    // wavefront of the last workgroup reads the color's last record), so
+    // the launch waits for one memory round trip before its schedule loads
+    const int task = task_base + min(local, ntasks_color - 1);
     const TaskRec tr = tasks[task];
-    if (tr.wide >= 0) return;   // run by k_sweep_wide
-    sweep_task<F, FWD, KMAX, MODE, TIn, TOut>(tr, chunks, meta, scol, sval, inv, in, out, cg, ys_all[wave],
-                                              cg.part ? cg.part + task : nullptr);
+    const bool running = *done_flag(sc) == DONE_RUNNING;   // sc is cg.sc
+    // one test of both (bitwise, so neither load waits for the other);
+    // wide tasks are run by k_sweep_wide
+    if (running & (local < ntasks_color) & (tr.wide < 0))
+        sweep_task<F, FWD, KMAX, MODE, TIn, TOut>(tr, chunks, meta, scol, sval, inv, in, out, cg,
+                                                  ys_all[wave], cg.part ? cg.part + task : nullptr);
+    // bumps the epoch of a dataflow launch that follows in the stream
+    if (running && bump && blockIdx.x == 0 && threadIdx.x == 0) *bump += 1;
 }
 
 // Block of right-hand sides (columns ld apart): workgroup g runs task g of
@@ -1004,12 +1044,13 @@ template <typename F, int KMAX>
 __global__ __launch_bounds__(64) void k_sweep_turn(SweepArgs<F> fa, SweepArgs<F> ba, int task_base,
                                                    int ntasks, F *__restrict__ y, double *__restrict__ z,
                                                    CgArgs f, CgArgs g) {
-    if (f.sc->done != DONE_RUNNING) return;
     __shared__ F ys[kChunkRows];
-    const int local = xcd_remap(blockIdx.x, gridDim.x);
-    if (local >= ntasks) return;
-    const int task = task_base + local;
+    const int local = xcd_remap(blockIdx.x, ntasks);   // the grid has ntasks workgroups
+    // task record and stopping flag read together, tested at once (as in
+    // k_sweep; the turn's color has no wide task)
+    const int task = task_base + min(local, ntasks - 1);
     const TaskRec tf = fa.tasks[task];
+    if ((f.sc->done != DONE_RUNNING) | (local >= ntasks) | (tf.wide >= 0)) return;
     sweep_task<F, true, KMAX, SW_CG_FWD, double, F>(tf, fa.chunks, fa.meta, fa.scol, fa.sval, fa.inv, nullptr,
                                                      y, f, ys, f.part + task);
     // the backward half reads this wavefront's stores: they complete first
@@ -1330,7 +1371,7 @@ int launch_spmv(iccg_ctx *c, int mode, const double *x, double *y, const double 
     dim3 grid(c->spmv_blocks), block(64);
     if (!part) part = c->part.p;
     if (c->prof) c->prof->begin(c->work);
-#define SPMV_ARGS c->n, c->nslices, c->sell_rec.p, c->sell_col.p, c->sell_val.p, x, y, b, part, sc
+#define SPMV_ARGS c->n, c->nslices, c->sell_rec.p, sc, c->sell_col.p, c->sell_val.p, x, y, b, part
 #define SPMV_W(M)                                                                              \
     switch (c->sell_wmax) {                                                                    \
         case 8: hipLaunchKernelGGL((k_spmv<M, 8>), grid, block, 0, c->work, SPMV_ARGS); break;   \
@@ -1468,7 +1509,7 @@ int launch_sweep_t(iccg_ctx *c, const void *in, void *out, const CgArgs &cg, boo
     // colors [tail, ncolors) run as one dataflow launch in the hybrid mode
     const int tail = c->opt.sweep_launch == 2 ? c->flow_tail : c->ncolors;
     const int tail_tasks = d.color_task_ptr[c->ncolors] - d.color_task_ptr[tail];
-#define SWEEP_ARGS a.tasks, a.chunks, a.meta, a.scol, a.sval, a.inv, t0, t1 - t0, bump, pin, pout, cg
+#define SWEEP_ARGS a.tasks, cg.sc, a.meta, a.scol, a.sval, a.inv, t0, t1 - t0, a.chunks, bump, pin, pout, cg
     int launched = 0;
     // wide tasks (per-color launches only): values and LDS-level pieces of
     // the blocks of more than 64 rows
@@ -1916,7 +1957,9 @@ int upload_setup(iccg_ctx *c, int n, const int *rowptr, const int *col, const do
 
     c->nslices = static_cast<int>(hs.sell.slice_off.size());
     {
-        std::vector<int4> rec(c->nslices);
+        // padded to whole wavefronts: a wavefront loads its records at once
+        const int nrec = (c->nslices + kSpmvSlicesPerWave - 1) / kSpmvSlicesPerWave * kSpmvSlicesPerWave;
+        std::vector<int4> rec(std::max(nrec, kSpmvSlicesPerWave), make_int4(0, 0, 0, 0));
         for (int lg = 0; lg < c->nslices; ++lg) {
             const int sl = hs.sell.order[lg];
             rec[lg] = make_int4(sl, hs.sell.slice_off[sl], hs.sell.slice_width[sl], 0);
