@@ -114,7 +114,11 @@ def solve_both(net: "iccg.Network", ctx, b_dev, tol: float = 1e-8, maxit: int = 
     out = {"plain_iters": plain["iters"], "plain_ms": plain_ms, "infer_ms": infer_ms,
            "setup_ms": max(first_ms - infer_ms, 0.0), "pivot_ok": accepted}
     if accepted:
+        # untimed first, as for the plain solve, so both timed solves start
+        # from the same state of the device
         x1 = torch.zeros(n, dtype=torch.float64, device="cuda")
+        ctx.solve(b_dev, x1, tol=tol, maxit=maxit, raise_on_noconv=False)
+        x1.zero_()
         lr_ = ctx.solve(b_dev, x1, tol=tol, maxit=maxit, raise_on_noconv=False)
         a, b = x1.cpu().numpy(), x0.cpu().numpy()
         out.update({"learned_iters": lr_["iters"], "learned_ms": ctx.info()["last_solve_ms"],
