@@ -276,7 +276,7 @@ def parse():
                     help="skip the FEM-like kNN and 27-point stencil entries")
     ap.add_argument("--leiden-seeds", default="9,31,42,58,74")
     ap.add_argument("--cpm-gammas", default="0.001,0.01,0.2")
-    ap.add_argument("--other-block-sizes", default="8,16,32",
+    ap.add_argument("--other-block-sizes", default="2,4,8,16,32",
                     help="ABMC block sizes swept on the kNN graph and the 27-point stencil")
     ap.add_argument("--md-gammas", default="4,16",
                     help="Leiden-MD resolutions for the kNN graph beside gamma = 1")

@@ -3,7 +3,7 @@ of each started in a background thread.
 
 The serial oracle needs 0.2-0.45 s per PCG iteration at these sizes, so one
 solve to 1e-8 takes 1.5-3 minutes (128^3 7-point: about 580 iterations;
-13-NN graph on 10^6 points: about 300; 27-point 96^3: about 350).  The
+13-NN graph on 10^6 points: about 310; 27-point 96^3: about 410).  The
 first full-size test module starts all three at once (the C call releases
 the GIL), the GPU tests run meanwhile, and the solution-parity module at the
 end of the session collects them.  Test infrastructure: the oracle and the
@@ -28,8 +28,8 @@ MAXIT = 5000
 # (the fastest of its block-size sweep)
 FULL = {
     "poisson7_128": 16,
-    "knn13_1m": 8,
-    "stencil27_96": 8,
+    "knn13_1m": 4,
+    "stencil27_96": 2,
 }
 
 _pool = ThreadPoolExecutor(max_workers=len(FULL))

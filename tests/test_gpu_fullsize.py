@@ -6,10 +6,10 @@ benchmark times (per-color launches, HIP graph batches of 32 iterations).
   application and SpMV element by element against the serial oracle (which
   finishes these single steps in well under a second); the solve to 1e-8
   checked by its true residual recomputed on the host.
-* 13-NN graph Laplacian on 10^6 points: ABMC(8, 32), Leiden-CPM(0.05) and
+* 13-NN graph Laplacian on 10^6 points: ABMC(4, 8, 32), Leiden-CPM(0.05) and
   Leiden-modularity orderings bit-exact; IC application on the Leiden
   orderings element by element; the solves by their true residual.
-* 27-point lognormal(sigma = 2) stencil on 96^3, ABMC(8), FP32 form: IC application
+* 27-point lognormal(sigma = 2) stencil on 96^3, ABMC(2), FP32 form: IC application
   against the oracle run on the factor rounded to FP32; the solve by its true
   residual and its distance from the FP64 solve.
 
@@ -190,7 +190,7 @@ def knn():
 
 def test_knn1m_orderings_bit_exact(knn):
     A, _ = knn
-    for s in (8, 32):
+    for s in (4, 8, 32):
         _same_order(iccg.iccg_order_abmc(A, s), oracle.order_abmc(A, s))
     _same_order(iccg.iccg_order_leiden(A, "modularity", 1.0),
                 oracle.order_leiden(A, "modularity", 1.0))

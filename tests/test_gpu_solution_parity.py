@@ -5,7 +5,7 @@ same permuted system to the same tolerance (Section 5: stop at
 
 Workloads: 3D 7-point lognormal Poisson 128^3 with ABMC block size 16 (the
 benchmark's timed configuration), the 13-NN graph Laplacian on 10^6 points
-and the 27-point lognormal stencil on 96^3, both with ABMC block size 8 (the
+and the 27-point lognormal stencil on 96^3, with ABMC block sizes 4 and 2 (the
 fastest of the benchmark's block-size sweep for them), all in FP64.
 
 Checked per workload:
