@@ -171,7 +171,7 @@ def tcc_summary(directory, command, out_file, label):
 def trace_summary(directory, command, out_file, label):
     """Kernel-time summary of one rocprofv3 --kernel-trace --stats run: the
     statistics table and one CG iteration in trace order (the dispatches
-    from one k_update_p to the next, in the middle of the last solve)."""
+    from one k_update_p to the next, the iteration of median span)."""
     stats = _csv_rows(directory, "kernel_stats.csv")
     trace = _csv_rows(directory, "kernel_trace.csv")
     tot = sum(float(r["TotalDurationNs"]) for r in stats)
@@ -193,8 +193,12 @@ def trace_summary(directory, command, out_file, label):
     trace.sort(key=lambda r: int(r["Start_Timestamp"]))
     ups = [i for i, r in enumerate(trace) if "k_update_p" in r["Kernel_Name"] and "cols" not in r["Kernel_Name"]]
     if len(ups) >= 4:
-        a = ups[len(ups) // 2 - 1]
-        b = ups[len(ups) // 2]
+        # the iteration of median span (a span that holds the host's check
+        # between two replayed batches is not one iteration's work)
+        spans = sorted((int(trace[ups[j + 1]]["Start_Timestamp"]) - int(trace[ups[j]]["Start_Timestamp"]), j)
+                       for j in range(len(ups) - 1))
+        j = spans[len(spans) // 2][1]
+        a, b = ups[j], ups[j + 1]
         seg = trace[a:b]
         span = (int(trace[b]["Start_Timestamp"]) - int(seg[0]["Start_Timestamp"])) / 1e3
         lines += ["", f"One CG iteration in trace order ({len(seg)} kernels, {span:.1f} us from the start of",

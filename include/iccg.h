@@ -229,7 +229,7 @@ int iccg_spmv(iccg_ctx *c, const double *p, double *q, double *pq_host);
  * (DEVICE p, q of n; pq_dev: one DEVICE double), enqueued on the context's
  * stream with no host synchronization; results equal iccg_spmv's bit for bit.
  * The per-workgroup partial sums live in a library-wide static device array of
- * 2^17 doubles (1 MiB per GPU, held until the process ends), so the call
+ * 2^18 doubles (2 MiB per GPU, held until the process ends), so the call
  * allocates nothing; every partial is rewritten before it is read, so nothing
  * needs clearing.  All calls on one GPU share that array: calls that overlap
  * on one GPU (other streams, other threads) race.  ICCG_EINVAL for n > 2^24

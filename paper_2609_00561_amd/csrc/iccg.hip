@@ -255,17 +255,23 @@ __global__ void k_init_scalars(DevScalars *sc, double tol, int maxit, int hist_c
 //   SP_RESID: y = b - A x, partial (y, y)
 // ---------------------------------------------------------------------------
 enum SpmvMode : int { SP_PLAIN = 0, SP_RESID = 1 };
-constexpr int kSpmvSlicesPerWave = 2;
-struct alignas(16 * kSpmvSlicesPerWave) SliceRecs {
-    int4 r[kSpmvSlicesPerWave];
+// Slices per wavefront: two for rows of up to 8 entries; one for wider rows,
+// whose WMAX slots per slice already keep enough loads in flight and whose
+// registers for two slices would leave one wavefront per SIMD (WMAX = 32).
+constexpr int spmv_slices_per_wave(int wmax) { return wmax <= 8 ? 2 : 1; }
+constexpr int kSpmvMaxSlicesPerWave = 2;
+template <int U>
+struct alignas(16 * U) SliceRecs {
+    int4 r[U];
 };
 // Columns (wavefronts) per workgroup of the block-of-right-hand-sides kernels.
 constexpr int kColWaves = 8;
 
-// One wavefront per kSpmvSlicesPerWave consecutive launch positions (the
-// grid has ceil(nslices / kSpmvSlicesPerWave) wavefronts); WMAX slots of a
-// row are loaded into registers at once, then all gathers, then the row sum
-// in ascending column order.  wg: the wavefront's logical index; lane 0
+// One wavefront per U = spmv_slices_per_wave(WMAX) consecutive launch
+// positions (the grid has ceil(nslices / U) wavefronts); the slots of a row
+// are taken in rounds of up to 16 (loads in registers at once, then the
+// gathers, then the terms), the row sum in ascending column order.  wg: the
+// wavefront's logical index; lane 0
 // writes the wavefront's partial sum to *part_out.  NT: stream the matrix
 // with non-temporal loads.  stop: the solve's stopping flag (the wavefront
 // returns at once unless it reads DONE_RUNNING).
@@ -275,7 +281,7 @@ __device__ __forceinline__ void spmv_wave(int n, int nslices, const int4 *__rest
                                           const double *__restrict__ x, double *__restrict__ y,
                                           const double *__restrict__ b, double *__restrict__ part_out,
                                           int wg, const int *stop) {
-    constexpr int U = kSpmvSlicesPerWave;
+    constexpr int U = spmv_slices_per_wave(WMAX);
     const int lane = static_cast<int>(threadIdx.x) & 63;
     const int lg0 = wg * U;
     // U consecutive launch positions at once, so one wavefront has all of
@@ -286,11 +292,10 @@ __device__ __forceinline__ void spmv_wave(int n, int nslices, const int4 *__rest
     // matrix loads; a stopped solve leaves every slice with no rows and no
     // slots, and then nothing else is loaded or stored but the partial sum
     // (zero).
-    const SliceRecs recs = reinterpret_cast<const SliceRecs *>(slices)[wg];
+    const SliceRecs<U> recs = reinterpret_cast<const SliceRecs<U> *>(slices)[wg];
     const bool running = *stop == DONE_RUNNING;
     int off[U], w[U], row[U];
-    int cc[U][WMAX];
-    double vv[U][WMAX], xv[U][WMAX], own_x[U], own_b[U];
+    double own_x[U], own_b[U], sum[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
         const bool valid = running && lg0 + u < nslices;
@@ -298,22 +303,8 @@ __device__ __forceinline__ void spmv_wave(int n, int nslices, const int4 *__rest
         off[u] = rec.y + lane;
         w[u] = valid ? rec.z : 0;
         row[u] = valid ? rec.x * 64 + lane : n;
+        sum[u] = 0.0;
     }
-    // the matrix streams through once (non-temporal: it should not push
-    // the gathered vector out of L2), unless several wavefronts read it
-#pragma unroll
-    for (int u = 0; u < U; ++u)
-#pragma unroll
-        for (int k = 0; k < WMAX; ++k)
-            if (k < w[u]) {
-                if (NT) {
-                    cc[u][k] = __builtin_nontemporal_load(col + off[u] + k * 64);
-                    vv[u][k] = __builtin_nontemporal_load(val + off[u] + k * 64);
-                } else {
-                    cc[u][k] = col[off[u] + k * 64];
-                    vv[u][k] = val[off[u] + k * 64];
-                }
-            }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
         own_x[u] = 0.0;
@@ -323,28 +314,55 @@ __device__ __forceinline__ void spmv_wave(int n, int nslices, const int4 *__rest
             if (MODE == SP_RESID) own_b[u] = b[row[u]];
         }
     }
+    // Slots in rounds of at most 16 (rows wider than 16 entries take two
+    // rounds, so a wavefront holds 16 slots' registers, not 32): every load
+    // of a round at once, then its gathers, then its terms in ascending
+    // column order.  The matrix streams through once (non-temporal: it
+    // should not push the gathered vector out of L2), unless several
+    // wavefronts read it.
+    constexpr int RS = WMAX < 16 ? WMAX : 16;
+#pragma unroll 1
+    for (int r0 = 0; r0 < WMAX; r0 += RS) {
+        int cc[U][RS];
+        double vv[U][RS], xv[U][RS];
 #pragma unroll
-    for (int u = 0; u < U; ++u)
+        for (int u = 0; u < U; ++u)
 #pragma unroll
-        for (int k = 0; k < WMAX; ++k)
-            if (k < w[u]) xv[u][k] = x[cc[u][k] < 0 ? 0 : cc[u][k]];
+            for (int j = 0; j < RS; ++j)
+                if (r0 + j < w[u]) {
+                    const int sl = off[u] + (r0 + j) * 64;
+                    if (NT) {
+                        cc[u][j] = __builtin_nontemporal_load(col + sl);
+                        vv[u][j] = __builtin_nontemporal_load(val + sl);
+                    } else {
+                        cc[u][j] = col[sl];
+                        vv[u][j] = val[sl];
+                    }
+                }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int j = 0; j < RS; ++j)
+                if (r0 + j < w[u]) xv[u][j] = x[cc[u][j] < 0 ? 0 : cc[u][j]];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int j = 0; j < RS; ++j)
+                if (r0 + j < w[u]) sum[u] = (cc[u][j] >= 0) ? sum[u] + vv[u][j] * xv[u][j] : sum[u];
+    }
     double acc = 0.0;
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-        double sum = 0.0;
-#pragma unroll
-        for (int k = 0; k < WMAX; ++k)
-            if (k < w[u]) sum = (cc[u][k] >= 0) ? sum + vv[u][k] * xv[u][k] : sum;
         for (int k = WMAX; k < w[u]; ++k) {
             const int c = col[off[u] + k * 64];
-            if (c >= 0) sum += val[off[u] + k * 64] * x[c];
+            if (c >= 0) sum[u] += val[off[u] + k * 64] * x[c];
         }
         if (row[u] < n) {
             if (MODE == SP_PLAIN) {
-                y[row[u]] = sum;
-                acc += own_x[u] * sum;
+                y[row[u]] = sum[u];
+                acc += own_x[u] * sum[u];
             } else {
-                const double rv = own_b[u] - sum;
+                const double rv = own_b[u] - sum[u];
                 y[row[u]] = rv;
                 acc += rv * rv;
             }
@@ -364,9 +382,10 @@ __global__ __launch_bounds__(64) void k_spmv(int n, int nslices, const int4 *__r
                                              double *__restrict__ y,
                                              const double *__restrict__ b,
                                              double *__restrict__ part) {
-    // the grid is ceil(nslices / kSpmvSlicesPerWave) (computed here rather than
-    // read from the dispatch packet, so the launch's first loads are its own)
-    const int grid = (nslices + kSpmvSlicesPerWave - 1) / kSpmvSlicesPerWave;
+    // the grid is ceil(nslices / U) (computed here rather than read from the
+    // dispatch packet, so the launch's first loads are its own)
+    constexpr int U = spmv_slices_per_wave(WMAX);
+    const int grid = (nslices + U - 1) / U;
     spmv_wave<MODE, WMAX, true>(n, nslices, slices, col, val, x, y, b, part + blockIdx.x,
                                 xcd_remap(blockIdx.x, grid), done_flag(sc));
 }
@@ -1323,12 +1342,13 @@ __global__ __launch_bounds__(64) void k_sweep_flow(const TaskRec *__restrict__ t
 // ---------------------------------------------------------------------------
 // static scratch of the allocation-free entry point (iccg_spmv_dot_noalloc)
 // ---------------------------------------------------------------------------
-// The SpMV's per-workgroup partial sums, one double per workgroup: 2^17 of
-// them cover n <= 2^24 rows.  Each GPU holds its own copy for the life of the
+// The SpMV's per-workgroup partial sums, one double per workgroup: 2^18 of
+// them cover n <= 2^24 rows (a workgroup covers 64 rows of a matrix with
+// rows wider than 8 entries, 128 otherwise).  Each GPU holds its own copy for the life of the
 // process; host code reaches it only through the address hipGetSymbolAddress
 // returns for the current device (resolved in iccg_setup), never through the
 // array's name.
-constexpr int kNoAllocParts = 1 << 17;
+constexpr int kNoAllocParts = 1 << 18;
 __device__ __align__(256) double scratch[kNoAllocParts];
 
 namespace {
@@ -1526,7 +1546,7 @@ int launch_sweep_t(iccg_ctx *c, const void *in, void *out, const CgArgs &cg, boo
         if (t1 - t0 > nw || bump) {
             ++launched;
             const dim3 grid((t1 - t0 + kSweepWaves - 1) / kSweepWaves), block(64 * kSweepWaves);
-            switch (d.kmax) {
+            switch (d.color_kmax[col]) {
                 case 4: hipLaunchKernelGGL((k_sweep<F, FWD, 4, MODE, TIn, TOut>), grid, block, 0, c->work, SWEEP_ARGS); break;
                 case 6: hipLaunchKernelGGL((k_sweep<F, FWD, 6, MODE, TIn, TOut>), grid, block, 0, c->work, SWEEP_ARGS); break;
                 case 8: hipLaunchKernelGGL((k_sweep<F, FWD, 8, MODE, TIn, TOut>), grid, block, 0, c->work, SWEEP_ARGS); break;
@@ -1649,7 +1669,7 @@ int launch_turn_t(iccg_ctx *c, const CgArgs &f, const CgArgs &g) {
     if (nt <= 0) return ICCG_OK;
     const SweepArgs<F> fa = sweep_args<F>(c, c->fwd), ba = sweep_args<F>(c, c->bwd);
     F *y = static_cast<F *>(ytmp(c));
-    const int K = std::max(c->fwd.kmax, c->bwd.kmax);
+    const int K = std::max(c->fwd.color_kmax[last], c->bwd.color_kmax[last]);
     const dim3 grid(nt), block(64);
 #define TURN_ARGS fa, ba, t0, nt, y, c->z.p, f, g
     switch (K) {
@@ -1791,13 +1811,22 @@ int upload_sweep(iccg_ctx *c, const SweepPlan &plan, DevSweep &d) {
     d.nslots = static_cast<long long>(plan.slot_col.size());
     d.max_depth = plan.max_depth;
     d.max_width = plan.max_width;
-    d.kmax = plan.max_width <= 4   ? 4
-             : plan.max_width <= 6 ? 6
-             : plan.max_width <= 8 ? 8
-             : plan.max_width <= 16 ? 16
-             : plan.max_width <= 28 ? 28
-                                    : 32;
+    auto tier = [](int w) { return w <= 4 ? 4 : w <= 6 ? 6 : w <= 8 ? 8 : w <= 16 ? 16 : w <= 28 ? 28 : 32; };
+    d.kmax = tier(plan.max_width);
     d.color_task_ptr = plan.color_task_ptr;
+    // the register tier of each color's launch follows the widest row of
+    // that color (in color-major order a row's lower entries grow with its
+    // color, so early forward colors need few slots); every tier computes
+    // the same terms in the same order
+    const int ncol = static_cast<int>(plan.color_task_ptr.size()) - 1;
+    d.color_kmax.assign(std::max(ncol, 0), 4);
+    for (int col = 0; col < ncol; ++col) {
+        int w = 0;
+        for (int t = plan.color_task_ptr[col]; t < plan.color_task_ptr[col + 1]; ++t)
+            for (int q = plan.task_chunk_ptr[t]; q < plan.task_chunk_ptr[t + 1]; ++q)
+                w = std::max(w, plan.chunks[q].width());
+        d.color_kmax[col] = tier(w);
+    }
     ICCG_CHECK(d.tasks.upload(plan.tasks.data(), plan.tasks.size(), c->work));
     d.ndeps = static_cast<long long>(plan.deps.size());
     ICCG_CHECK(d.deps.upload(plan.deps.data(), plan.deps.size(), c->work));
@@ -1958,8 +1987,8 @@ int upload_setup(iccg_ctx *c, int n, const int *rowptr, const int *col, const do
     c->nslices = static_cast<int>(hs.sell.slice_off.size());
     {
         // padded to whole wavefronts: a wavefront loads its records at once
-        const int nrec = (c->nslices + kSpmvSlicesPerWave - 1) / kSpmvSlicesPerWave * kSpmvSlicesPerWave;
-        std::vector<int4> rec(std::max(nrec, kSpmvSlicesPerWave), make_int4(0, 0, 0, 0));
+        const int nrec = (c->nslices + kSpmvMaxSlicesPerWave - 1) / kSpmvMaxSlicesPerWave * kSpmvMaxSlicesPerWave;
+        std::vector<int4> rec(std::max(nrec, kSpmvMaxSlicesPerWave), make_int4(0, 0, 0, 0));
         for (int lg = 0; lg < c->nslices; ++lg) {
             const int sl = hs.sell.order[lg];
             rec[lg] = make_int4(sl, hs.sell.slice_off[sl], hs.sell.slice_width[sl], 0);
@@ -1974,8 +2003,9 @@ int upload_setup(iccg_ctx *c, int n, const int *rowptr, const int *col, const do
     int wmax = 0;
     for (int w : hs.sell.slice_width) wmax = std::max(wmax, w);
     c->sell_wmax = wmax <= 8 ? 8 : wmax <= 16 ? 16 : 32;
-    // one wavefront per kSpmvSlicesPerWave slices, in launch order
-    c->spmv_blocks = (c->nslices + kSpmvSlicesPerWave - 1) / kSpmvSlicesPerWave;
+    // one wavefront per spmv_slices_per_wave(wmax) slices, in launch order
+    const int spw = spmv_slices_per_wave(c->sell_wmax);
+    c->spmv_blocks = (c->nslices + spw - 1) / spw;
     c->vec_blocks = round8(grid_for(n, kVecThreads, kMaxVecBlocks));
     const int np = std::max({c->spmv_blocks, c->vec_blocks, c->bwd.ntasks, c->fwd.ntasks, 1});
     ICCG_CHECK(c->part.alloc(np));
@@ -2105,7 +2135,7 @@ int launch_sweep_cols_t(iccg_ctx *c, int k, const void *in, void *out, const CgA
         if (t1 == t0) continue;
         const dim3 grid(t1 - t0, (k + kColWaves - 1) / kColWaves), block(64 * std::min(k, kColWaves));
 #define COLS_ARGS a.tasks, a.chunks, a.meta, a.scol, a.sval, a.inv, t0, t1 - t0, pin, pout, cg, ld, part_ld, k
-        switch (d.kmax) {
+        switch (d.color_kmax[col]) {
             case 4: hipLaunchKernelGGL((k_sweep_cols<F, FWD, 4, MODE, TIn, TOut>), grid, block, 0, c->work, COLS_ARGS); break;
             case 6: hipLaunchKernelGGL((k_sweep_cols<F, FWD, 6, MODE, TIn, TOut>), grid, block, 0, c->work, COLS_ARGS); break;
             case 8: hipLaunchKernelGGL((k_sweep_cols<F, FWD, 8, MODE, TIn, TOut>), grid, block, 0, c->work, COLS_ARGS); break;

@@ -99,7 +99,8 @@ struct DevSweep {
     long long nslots = 0;
     int max_depth = 0;
     int max_width = 0;
-    int kmax = 4;                      // register slots per row in k_sweep
+    int kmax = 4;                      // register slots per row (widest row of the sweep)
+    std::vector<int> color_kmax;       // per color: the tier of its widest row
     std::vector<int> color_task_ptr;
     DevArray<TaskRec> tasks;
     DevArray<Chunk> chunks;
