@@ -160,7 +160,9 @@ def test_forward_independent_of_packing():
         assert np.array_equal(o, outs[0])
 
 
-@pytest.mark.parametrize("case", [CASES[0], CASES[5], CASES[7]], ids=_ids)
+# laplace2d_64: two slices per wavefront; knn13_20k, stencil27_12: one slice
+# per wavefront in rounds of 16 slots; randspd_2k: rows beyond 32 entries
+@pytest.mark.parametrize("case", [CASES[0], CASES[5], CASES[7], CASES[9]], ids=_ids)
 def test_spmv_and_dot_parity(case):
     cs = _case(*case)
     Ap = cs[4]
