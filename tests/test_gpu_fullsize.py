@@ -2,7 +2,7 @@
 benchmark times (per-color launches, HIP graph batches of 32 iterations).
 
 * 3D 7-point lognormal Poisson 128^3 (n = 2,097,152), ABMC block sizes
-  8/16/32/64: orderings bit-exact; factor, forward, backward, IC
+  2/4/8/16/32/64: orderings bit-exact; factor, forward, backward, IC
   application and SpMV element by element against the serial oracle (which
   finishes these single steps in well under a second); the solve to 1e-8
   checked by its true residual recomputed on the host.
@@ -102,7 +102,7 @@ def poisson():
     ctx.close()
 
 
-@pytest.mark.parametrize("s", [8, 32, 64])
+@pytest.mark.parametrize("s", [2, 4, 8, 32, 64])
 def test_poisson128_abmc_orderings_bit_exact(s):
     A, _ = _workload("poisson7_128")
     _same_order(iccg.iccg_order_abmc(A, s), oracle.order_abmc(A, s))
