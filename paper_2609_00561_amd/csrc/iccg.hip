@@ -1344,10 +1344,11 @@ __global__ __launch_bounds__(64) void k_sweep_flow(const TaskRec *__restrict__ t
 // ---------------------------------------------------------------------------
 // The SpMV's per-workgroup partial sums, one double per workgroup: 2^18 of
 // them cover n <= 2^24 rows (a workgroup covers 64 rows of a matrix with
-// rows wider than 8 entries, 128 otherwise).  Each GPU holds its own copy for the life of the
-// process; host code reaches it only through the address hipGetSymbolAddress
-// returns for the current device (resolved in iccg_setup), never through the
-// array's name.
+// rows wider than 8 entries, 128 otherwise).  Each GPU holds its own copy
+// for the life of the process; host code reaches it only through the
+// address hipGetSymbolAddress returns for the current device (resolved in
+// iccg_setup), never through the array's name.
+constexpr int kNoAllocMaxRows = 1 << 24;
 constexpr int kNoAllocParts = 1 << 18;
 __device__ __align__(256) double scratch[kNoAllocParts];
 
@@ -2605,7 +2606,7 @@ int iccg_spmv(iccg_ctx *c, const double *p, double *q, double *pq_host) {
 int iccg_spmv_dot_noalloc(iccg_ctx *c, const double *p, double *q, double *pq_dev) {
     return entry(c, [&]() -> int {
         if (!p || !q || !pq_dev || p == q) return set_error(ICCG_EINVAL, "need distinct p, q and a device pq");
-        if (c->spmv_blocks > kNoAllocParts)
+        if (c->n > kNoAllocMaxRows || c->spmv_blocks > kNoAllocParts)
             return set_error(ICCG_EINVAL, "iccg_spmv_dot_noalloc: n = " + std::to_string(c->n) +
                                               " exceeds the static scratch (at most 2^24 rows)");
         double *part = scratch_for(c->device);
