@@ -75,10 +75,25 @@ def _counter_rows(directory):
     return rows
 
 
-def traffic_file(workload, block_size):
-    if workload == "poisson7_128" and block_size == 16:
+def traffic_file(workload, block_size, tag=None):
+    if workload == "poisson7_128" and block_size == 16 and tag is None:
         return TRAFFIC_FILE
-    return os.path.join(ROOT, "profiles", f"traffic_sweep_spmv_{workload}_abmc{block_size}.md")
+    return os.path.join(ROOT, "profiles", f"traffic_sweep_spmv_{workload}_{tag or f'abmc{block_size}'}.md")
+
+
+# the orderings the profiling program can use besides ABMC (the paper's
+# Leiden-CPM at its resolution 0.05 and Leiden-MD at resolution 1)
+PROFILE_LEIDEN = {"leiden-cpm": ("cpm", 0.05, "Leiden-CPM gamma=0.05"),
+                  "leiden-md": ("modularity", 1.0, "Leiden-MD gamma=1")}
+
+
+def profile_ordering(args):
+    """(file tag, label) of the ordering the profiling program runs."""
+    if args.ordering == "abmc":
+        s = int(args.block_sizes.split(",")[0])
+        return f"abmc{s}", f"{args.workload} (ABMC s={s})"
+    quality, gamma, label = PROFILE_LEIDEN[args.ordering]
+    return args.ordering.replace("-", ""), f"{args.workload} ({label})"
 
 
 def traffic_summary(fetch_dir, write_dir, command_fetch, command_write, out_file=TRAFFIC_FILE,
@@ -244,8 +259,11 @@ def traffic_run(args):
     torch.cuda.synchronize()
     del x, y
     A, b = synth.workload(args.workload, args.seed)
-    s = int(args.block_sizes.split(",")[0])
-    order = iccg.iccg_order_abmc(A, s)
+    if args.ordering == "abmc":
+        order = iccg.iccg_order_abmc(A, int(args.block_sizes.split(",")[0]))
+    else:
+        quality, gamma, _ = PROFILE_LEIDEN[args.ordering]
+        order = iccg.iccg_order_leiden(A, quality, gamma)
     rp, cl, vl = iccg.iccg_permute(A, order.perm)
     # --unfused: the last color's sweeps as two launches, so the counted
     # forward-sweep dispatches are the n_c per-color launches the roofline's
@@ -270,6 +288,8 @@ def parse():
     ap.add_argument("--extra-block-sizes", default="2,4",
                     help="smaller ABMC block sizes also solved and reported, outside the headline sweep")
     ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--ordering", default="abmc", choices=["abmc"] + sorted(PROFILE_LEIDEN),
+                    help="ordering of the profiling program (--traffic-run) and its summaries")
     ap.add_argument("--no-leiden", action="store_true")
     ap.add_argument("--no-hybrid", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
@@ -451,16 +471,18 @@ def other_matrices(B, args, synth):
 def main():
     args = parse()
     s0 = int(args.block_sizes.split(",")[0])
-    label = f"{args.workload} (ABMC s={s0})"
+    tag, label = profile_ordering(args)
     if args.traffic_summary:
-        traffic_summary(*args.traffic_summary, out_file=traffic_file(args.workload, s0), label=label)
+        traffic_summary(*args.traffic_summary,
+                        out_file=traffic_file(args.workload, s0, None if args.ordering == "abmc" else tag),
+                        label=label)
         return
     if args.tcc_summary:
-        tcc_summary(*args.tcc_summary, os.path.join(ROOT, "profiles", f"l2_hit_sweep_spmv_{args.workload}_abmc{s0}.md"),
+        tcc_summary(*args.tcc_summary, os.path.join(ROOT, "profiles", f"l2_hit_sweep_spmv_{args.workload}_{tag}.md"),
                     label)
         return
     if args.trace_summary:
-        trace_summary(*args.trace_summary, os.path.join(ROOT, "profiles", f"kernels_iccg_solve_{args.workload}_abmc{s0}.md"),
+        trace_summary(*args.trace_summary, os.path.join(ROOT, "profiles", f"kernels_iccg_solve_{args.workload}_{tag}.md"),
                       label)
         return
     if args.gpus != 1:
