@@ -42,6 +42,8 @@ CALIB_ELEMS = 1 << 26
 KERNEL_CLASSES = {            # rocprofv3 kernel name pattern -> report name
     "k_sweep(forward)": r"k_sweep<double, true, \d+, 1,",
     "k_sweep(backward)": r"k_sweep<double, false, \d+, 2,",
+    "k_sweep_wide(forward)": r"k_sweep_wide<double, true, \d+, 1,",
+    "k_sweep_wide(backward)": r"k_sweep_wide<double, false, \d+, 2,",
     "k_spmv": r"k_spmv<0,",
     "calibration": r"neg",
 }
